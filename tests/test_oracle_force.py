@@ -1,0 +1,124 @@
+"""Pins of the oracle's density and mean-field forces (no GPU).
+
+Each force is checked against an independent evaluation of eq. (meanforce),
+F(x) = -d/dx int V(x - x') rho(x') dx', written here directly from the pair
+potentials of Sec. 2 (eqs. ringpot, hmfpot, sheetpot) with exactly rounded
+sums, and against the paper's limits (ring -> HMF for large softening).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1206_3229_amd import inputs as I
+
+
+def _params(model, nx, np_=16, **kw):
+    if model == I.MODEL_SHEET:
+        return I.Params(model, nx, np_, -3.0, 3.0, -2.0, 2.0, 0.1, bc_x=I.BC_ZERO, **kw)
+    return I.Params(model, nx, np_, -math.pi, math.pi, -2.0, 2.0, 0.1, **kw)
+
+
+def _rho(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, 1.0, n) * (1.0 + np.cos(np.linspace(0, 2 * np.pi, n, endpoint=False)))
+
+
+@pytest.mark.parametrize("nx,np_", [(16, 16), (33, 17), (64, 130), (128, 64)])
+def test_density_is_the_momentum_integral(oracle, nx, np_):
+    p = _params(I.MODEL_HMF, nx, np_)
+    f = np.random.default_rng(nx + np_).standard_normal((np_, nx))
+    rho = oracle.density(p, f)
+    for i in range(nx):
+        want = p.dp * math.fsum(f[:, i].tolist())
+        assert abs(rho[i] - want) <= 1e-15 * p.dp * np.abs(f[:, i]).sum()
+
+
+@pytest.mark.parametrize("nx", [16, 64, 100])
+def test_hmf_force_is_the_sine_convolution(oracle, nx):
+    # eq. (hmfpot): V = 1 - cos(d)  =>  F_i = -dx sum_k sin(x_i - x_k) rho_k
+    p = _params(I.MODEL_HMF, nx)
+    rho = _rho(nx, 1)
+    F, (mx, my) = oracle.force(p, rho)
+    x = I.nodes(nx, p.xmin, p.xmax)
+    for i in range(nx):
+        want = -p.dx * math.fsum((np.sin(x[i] - x) * rho).tolist())
+        assert abs(F[i] - want) < 1e-14 * rho.sum() * p.dx * 4
+    # eq. (mxmydef)
+    assert abs(mx - p.dx * math.fsum((np.cos(x) * rho).tolist())) < 1e-15 * 8
+    assert abs(my - p.dx * math.fsum((np.sin(x) * rho).tolist())) < 1e-15 * 8
+
+
+@pytest.mark.parametrize("nx", [16, 64, 129])
+def test_ring_force_derivative_of_potential(oracle, nx):
+    # eq. (ringpot) with eps = 0.5: F(x_i) = -d/dx [dx sum_k V(x - x_k) rho_k] at x_i,
+    # derivative taken by a 4th-order central difference of the potential sum.
+    p = _params(I.MODEL_RING, nx, ring_eps=0.5)
+    rho = _rho(nx, 2)
+    F, _ = oracle.force(p, rho)
+    x = I.nodes(nx, p.xmin, p.xmax)
+
+    def phi(y):
+        q = 2.0 * (1.0 + 0.5 - np.cos(y - x))
+        return p.dx * math.fsum((-rho / np.sqrt(q)).tolist())
+
+    h = 1e-3
+    for i in range(nx):
+        d = (-phi(x[i] + 2 * h) + 8 * phi(x[i] + h) - 8 * phi(x[i] - h) + phi(x[i] - 2 * h)) / (12 * h)
+        # the separation n/2 (antipode) is zeroed in the table; its exact derivative is 0 too
+        assert abs(F[i] + d) < 1e-9, (i, F[i], -d)
+
+
+def test_ring_tends_to_hmf_for_large_softening(oracle):
+    # Sec. 2: for increasing eps the ring model tends to the HMF model,
+    # V'_ring(d) = sin d (2(1+eps-cos d))^{-3/2} -> sin d (2(1+eps))^{-3/2}.
+    nx, eps = 64, 1e6
+    rho = _rho(nx, 3)
+    Fr, _ = oracle.force(_params(I.MODEL_RING, nx, ring_eps=eps), rho)
+    Fh, _ = oracle.force(_params(I.MODEL_HMF, nx), rho)
+    scale = (2.0 * (1.0 + eps)) ** -1.5
+    assert np.max(np.abs(Fr - scale * Fh)) < 3e-6 * scale * np.max(np.abs(Fh))
+
+
+def test_ring_tables_symmetry(oracle):
+    p = _params(I.MODEL_RING, 64, ring_eps=0.01)
+    dV, V = oracle.ring_tables(p)
+    assert dV[0] == 0.0 and dV[32] == 0.0
+    assert np.array_equal(dV[1:32], -dV[63:32:-1])
+    assert np.array_equal(V[1:32], V[63:32:-1])
+    assert abs(V[0] + 1.0 / math.sqrt(2 * 0.01)) < 1e-12 * abs(V[0])
+    # largest attraction near d = sqrt(2 eps)-ish: max |V'| of the softened potential
+    d = np.linspace(1e-4, 0.5, 200001)
+    peak = np.max(np.sin(d) / (2 * (1.01 - np.cos(d))) ** 1.5)
+    assert abs(peak - 19.22) < 0.01
+
+
+@pytest.mark.parametrize("nx", [1, 5, 63, 64, 65, 130, 4096])
+def test_sheet_force_is_the_sign_sum(oracle, nx):
+    # eq. (sheetpot) with V = 2 pi G |x|: F_i = 2 pi G dx sum_k sign(x_k - x_i) rho_k
+    p = _params(I.MODEL_SHEET, nx, sheet_G=1.3)
+    rho = _rho(nx, 4)
+    F, _ = oracle.force(p, rho)
+    tot = math.fsum(rho.tolist())
+    for i in range(0, nx, max(1, nx // 97)):
+        above = math.fsum(rho[i + 1:].tolist())
+        below = math.fsum(rho[:i].tolist())
+        want = 2 * math.pi * 1.3 * p.dx * (above - below)
+        assert abs(F[i] - want) < 1e-14 * 2 * math.pi * 1.3 * p.dx * tot * 4, (i, F[i], want)
+
+
+def test_forces_are_antisymmetric_in_total(oracle):
+    # sum_i F_i rho_i = 0 (action = reaction), hence momentum conservation
+    for model in (I.MODEL_HMF, I.MODEL_RING, I.MODEL_SHEET):
+        p = _params(model, 96)
+        rho = _rho(96, 5)
+        F, _ = oracle.force(p, rho)
+        s = math.fsum((F * rho).tolist())
+        assert abs(s) < 1e-13 * math.fsum(np.abs(F * rho).tolist())
+
+
+def test_external_force_passthrough(oracle):
+    p = _params(I.MODEL_EXTERNAL, 32)
+    Fe = np.linspace(-1, 1, 32)
+    F, _ = oracle.force(p, np.ones(32), Fe)
+    assert np.array_equal(F, Fe)
