@@ -1,0 +1,191 @@
+/*
+ * vlasov.h - C ABI of the MI355X (gfx950) solver for the one-dimensional
+ * Vlasov equation with long-range mean-field forces, after T. M. Rocha Filho,
+ * "Solving the Vlasov equation for one-dimensional models with long range
+ * interactions on a GPU" (arXiv:1206.3229).
+ *
+ * The distribution f(x, p, t) lives on an nx-by-np grid in device memory,
+ * row-major f[j*nx + i] with i the position index and j the momentum index
+ * (the layout of Sec. 3).  Axis u in [umin, umax) has nodes
+ * u_k = umin + k*du, du = (umax - umin)/n.  One time step is the time split of
+ * Sec. 3, steps 1-4 (eqs. step1-step4): half drift in x, mean-field force from
+ * the drifted f (eq. step2), full kick in p, half drift in x.  Every sweep
+ * evaluates the cubic spline of eqs. (splinegen, splinecoeffs) at the foot of
+ * the characteristic with second derivatives from the eighth-order stencil of
+ * eq. (findif).
+ *
+ * Conventions for every call:
+ *   - Status: 0 (VLASOV_OK) on success, VLASOV_PENDING (1) from poll only,
+ *     a negative VLASOV_E_* code on failure.  vlasov_last_error() returns the
+ *     message of the last failure on the calling thread.
+ *   - Device memory is owned by the caller (the library never allocates device
+ *     memory): the f pair, the workspace and the server arena are passed in as
+ *     plain device pointers, 256-byte aligned, and must outlive the context.
+ *   - hip_stream is a hipStream_t passed as void* (NULL: the null stream).
+ *     Work is enqueued asynchronously on it; only calls that return host data
+ *     synchronise it.
+ *   - Host buffers are read during the call only, and written only on success.
+ *   - A context is not thread-safe; a server is (submit and poll may be called
+ *     from any thread).
+ *   - A failed call leaves the context as it was, except after VLASOV_E_HIP.
+ */
+#ifndef VLASOV_H
+#define VLASOV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    VLASOV_OK = 0,
+    VLASOV_PENDING = 1,
+    VLASOV_E_INVAL = -1,     /* invalid argument */
+    VLASOV_E_NOMEM = -2,     /* request larger than the whole server arena */
+    VLASOV_E_HIP = -3,       /* a HIP runtime error (message has its string) */
+    VLASOV_E_STATE = -4,     /* call not valid in the current state */
+    VLASOV_E_NOTFOUND = -5,  /* unknown ticket */
+    VLASOV_E_NONFINITE = -6  /* a diagnostic came out NaN or infinite */
+};
+
+/* Pair potentials of Sec. 2: HMF (eq. hmfpot), ring (eq. ringpot) and
+ * self-gravitating sheets (eq. sheetpot, with V = 2 pi G |x|), plus a fixed
+ * force F(x) given by the caller. */
+typedef enum {
+    VLASOV_MODEL_HMF = 0,
+    VLASOV_MODEL_RING = 1,
+    VLASOV_MODEL_SHEET = 2,
+    VLASOV_MODEL_EXTERNAL = 3
+} vlasov_model;
+
+/* Storage of f between sweeps.  Densities, forces, foot positions and all
+ * diagnostics are computed in FP64 for both. */
+typedef enum { VLASOV_F64 = 0, VLASOV_F32 = 1 } vlasov_storage;
+
+/* Boundary of an axis: periodic, or zero extension (every sample outside the
+ * grid reads 0; mass advected out of the box is lost). */
+typedef enum { VLASOV_BC_PERIODIC = 0, VLASOV_BC_ZERO = 1 } vlasov_bc;
+
+typedef struct {
+    int32_t model;    /* vlasov_model */
+    int32_t storage;  /* vlasov_storage */
+    int32_t bc_x;     /* vlasov_bc; HMF and ring require periodic */
+    int32_t bc_p;     /* vlasov_bc */
+    int64_t nx, np;   /* grid points, 16 <= n <= 2^19 each, nx*np < 2^31 */
+    double xmin, xmax, pmin, pmax;
+    double dt;        /* time step, finite and nonzero */
+    double ring_eps;  /* softening of eq. (ringpot), > 0 (ring only) */
+    double sheet_G;   /* coupling of the sheet model, F = 2 pi G (M(>x) - M(<x)) */
+    int64_t hist_cap; /* entries kept of the per-step magnetization history (>= 0) */
+} vlasov_params;
+
+/* Diagnostics of the current f (rectangle rule on the grid):
+ * mass = int f, momentum = int p f, kinetic = int p^2/2 f, potential W of the
+ * model (HMF (M^2_0 - M_x^2 - M_y^2)/2 with M_0 the mass; ring and sheet the
+ * double sum 1/2 int int V(x-x') rho rho'; external 0), energy = kinetic + W,
+ * (mx, my) the magnetization of eq. (mxmydef) (HMF and ring; 0 otherwise),
+ * l2 = int f^2 (a Casimir of eq. casimirs). */
+typedef struct {
+    double mass, momentum, kinetic, potential, energy, mx, my, l2;
+} vlasov_moments_t;
+
+typedef struct vlasov_ctx vlasov_ctx;
+
+/* ---------------------------------------------------------------------------
+ * Single simulation.
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of the device f pair: 2 * nx * np * (8 for F64, 4 for F32).  0 if the
+ * parameters are invalid. */
+size_t vlasov_f_bytes(const vlasov_params *p);
+
+/* Bytes of the device workspace (line tables, density partial sums, density,
+ * force, magnetization history, diagnostics).  0 if invalid. */
+size_t vlasov_workspace_bytes(const vlasov_params *p);
+
+/* Create a context.  f0_host: nx*np FP64 values, row-major [np][nx], copied
+ * (rounded to nearest FP32 for F32 storage).  f_dev: vlasov_f_bytes() bytes;
+ * ws_dev: vlasov_workspace_bytes() bytes.  Builds the drift line tables
+ * (constant over the run) and the model tables on the host and uploads them.
+ * Synchronises hip_stream before returning.  Errors: VLASOV_E_INVAL for bad
+ * parameters (see vlasov_params), NULL or misaligned pointers; VLASOV_E_HIP. */
+int vlasov_init(const vlasov_params *p, const double *f0_host, void *f_dev, void *ws_dev, void *hip_stream,
+                vlasov_ctx **out);
+
+/* EXTERNAL model only: set the force F(x_i), nx FP64 values (copied).
+ * VLASOV_E_STATE on other models. */
+int vlasov_set_external_force(vlasov_ctx *c, const double *F_host);
+
+/* Enqueue nsteps (>= 0) time steps of Sec. 3 (steps 1-4).  Consecutive half
+ * drifts of successive steps are fused into one pass over f; the result is
+ * bit-identical to nsteps separate steps. */
+int vlasov_step(vlasov_ctx *c, int64_t nsteps);
+
+/* The individual sweeps of a step, for inspection and testing.
+ * vlasov_drift: npass (1 or 2) successive half drifts (eqs. step1/step4) of
+ *   the current f, tau = dt/2 each; also leaves the density partial sums of
+ *   the result.
+ * vlasov_force: density of the current f and the model force (eq. step2);
+ *   writes F (nx values) and the magnetization (2 values) to the host if the
+ *   pointers are non-NULL (then synchronises), and keeps F for the kick.
+ * vlasov_kick: the momentum advection of eq. (step3) with the last force;
+ *   VLASOV_E_STATE if no force was computed yet. */
+int vlasov_drift(vlasov_ctx *c, int32_t npass);
+int vlasov_force(vlasov_ctx *c, double *F_host, double *mxmy_host);
+int vlasov_kick(vlasov_ctx *c);
+
+/* Diagnostics of the current f; synchronises.  VLASOV_E_NONFINITE (out still
+ * written) if any value is NaN or infinite. */
+int vlasov_moments(vlasov_ctx *c, vlasov_moments_t *out);
+
+/* Per-step magnetization (M_x, M_y) of the drifted f used by each force
+ * evaluation (HMF and ring), oldest first.  Copies min(count, cap, hist_cap)
+ * entries, sets *count to the number of steps recorded so far; synchronises. */
+int vlasov_mag_history(vlasov_ctx *c, double *mx, double *my, int64_t cap, int64_t *count);
+
+/* Copy the current f to the host as FP64 [np][nx]; synchronises. */
+int vlasov_read_f(vlasov_ctx *c, double *f_host);
+
+/* Replace the current f (checkpoint restore), FP64 [np][nx]; synchronises. */
+int vlasov_write_f(vlasov_ctx *c, const double *f_host);
+
+/* Release the context (host memory only; caller device memory is untouched).
+ * Synchronises the stream first. */
+int vlasov_destroy(vlasov_ctx *c);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *vlasov_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Measurement.
+ * ------------------------------------------------------------------------- */
+
+/* Kernel identifiers for the per-kernel timers. */
+enum {
+    VLASOV_K_DRIFT = 0,    /* one half drift + density partial sums */
+    VLASOV_K_DRIFT2 = 1,   /* two fused half drifts + density partial sums */
+    VLASOV_K_DENSITY = 2,  /* density from the partial sums */
+    VLASOV_K_FORCE = 3,    /* model force (and magnetization) */
+    VLASOV_K_KICK = 4,     /* momentum advection */
+    VLASOV_K_MOMENTS = 5,  /* diagnostics */
+    VLASOV_K_COUNT = 6
+};
+
+/* When on, every kernel launch of the context is bracketed by HIP events on
+ * its stream.  vlasov_profile_read synchronises, folds the recorded launches
+ * of kernel `kernel` into the running totals and returns them (total
+ * milliseconds and number of launches since profiling was switched on). */
+int vlasov_profile_enable(vlasov_ctx *c, int32_t on);
+int vlasov_profile_read(vlasov_ctx *c, int32_t kernel, double *total_ms, int64_t *launches);
+const char *vlasov_kernel_name(int32_t kernel);
+
+/* Plain device-to-device copy of `bytes` (multiple of 16) with the library's
+ * own streaming kernel, for a measured bandwidth ceiling.  Asynchronous. */
+int vlasov_device_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VLASOV_H */

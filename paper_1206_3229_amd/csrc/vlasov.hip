@@ -1,0 +1,644 @@
+// Host runtime and C ABI of the gfx950 Vlasov solver (include/vlasov.h).
+//
+// A context owns no device memory: f (two ping-pong buffers) and the
+// workspace are caller allocations.  Host code builds the line tables of the
+// x drift (constant over a run) and the model tables (sin/cos of the angle
+// nodes, ring-potential derivative and value) with the host libm and uploads
+// them once; no transcendental function is evaluated on the device.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "vlasov.h"
+#include "vlasov_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                                   \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess) return fail(VLASOV_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+constexpr int DRIFT_TW = 256;
+constexpr int KICK_R = 16;
+
+// Workspace layout (byte offsets, each 256-aligned).
+struct Layout {
+    size_t drift_m, drift_w, part, rho, F, Fext, cs, sn, ringK, ringV, mxmy, hist, hcount, mom_out, mom_col,
+        mom_phi;
+    size_t total;
+};
+
+int64_t nblocks(int64_t np) { return (np + vk::ROWS_PER_BLOCK - 1) / vk::ROWS_PER_BLOCK; }
+
+Layout layout_of(const vlasov_params &p)
+{
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += align_up(bytes > 0 ? bytes : 1);
+        return at;
+    };
+    const size_t nx = (size_t)p.nx, np = (size_t)p.np;
+    L.drift_m = take(np * sizeof(int32_t));
+    L.drift_w = take(np * sizeof(double4));
+    L.part = take((size_t)nblocks(p.np) * nx * sizeof(double));
+    L.rho = take(nx * sizeof(double));
+    L.F = take(nx * sizeof(double));
+    L.Fext = take(nx * sizeof(double));
+    L.cs = take(nx * sizeof(double));
+    L.sn = take(nx * sizeof(double));
+    L.ringK = take(nx * sizeof(double));
+    L.ringV = take(nx * sizeof(double));
+    L.mxmy = take(2 * sizeof(double));
+    L.hist = take((size_t)p.hist_cap * 2 * sizeof(double));
+    L.hcount = take(sizeof(int64_t));
+    L.mom_out = take(8 * sizeof(double));
+    L.mom_col = take(4 * nx * sizeof(double));
+    L.mom_phi = take(nx * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+std::string validate(const vlasov_params *p)
+{
+    if (!p) return "params is NULL";
+    if (p->model < 0 || p->model > 3) return "unknown model";
+    if (p->storage != VLASOV_F64 && p->storage != VLASOV_F32) return "unknown storage";
+    if ((p->bc_x != 0 && p->bc_x != 1) || (p->bc_p != 0 && p->bc_p != 1)) return "unknown boundary";
+    if (p->nx < 16 || p->np < 16) return "nx and np must be >= 16";
+    // grid.y of the row-block launches is ceil(np/16) <= 65535
+    if (p->nx > (1 << 19) || p->np > (1 << 19) || p->nx * p->np >= ((int64_t)1 << 31)) return "grid too large";
+    if (!(isfinite(p->xmin) && isfinite(p->xmax) && p->xmax > p->xmin)) return "bad x domain";
+    if (!(isfinite(p->pmin) && isfinite(p->pmax) && p->pmax > p->pmin)) return "bad p domain";
+    if (!isfinite(p->dt) || p->dt == 0.0) return "dt must be finite and nonzero";
+    if ((p->model == VLASOV_MODEL_HMF || p->model == VLASOV_MODEL_RING) && p->bc_x != VLASOV_BC_PERIODIC)
+        return "HMF and ring models need a periodic x axis";
+    if (p->model == VLASOV_MODEL_RING && !(isfinite(p->ring_eps) && p->ring_eps > 0.0)) return "ring_eps must be > 0";
+    if (p->model == VLASOV_MODEL_SHEET && !isfinite(p->sheet_G)) return "sheet_G must be finite";
+    if (p->hist_cap < 0) return "hist_cap must be >= 0";
+    return "";
+}
+
+}  // namespace
+
+struct vlasov_ctx {
+    vlasov_params P;
+    hipStream_t stream;
+    size_t s;  // bytes per stored value
+    char *f[2];
+    int cur;
+    char *ws;
+    Layout L;
+    double dx, dp;
+    int64_t nblk;
+    bool have_force;
+    // host copies kept alive for asynchronous uploads
+    std::vector<int32_t> h_dm;
+    std::vector<double4> h_dw;
+    // profiling
+    bool prof;
+    struct Rec {
+        int kid;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    double ms[VLASOV_K_COUNT];
+    int64_t cnt[VLASOV_K_COUNT];
+
+    template <typename U> U *at(size_t off) const { return reinterpret_cast<U *>(ws + off); }
+    void *fcur() const { return f[cur]; }
+    void *fnext() const { return f[cur ^ 1]; }
+};
+
+namespace {
+
+hipEvent_t take_event(vlasov_ctx *c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one launch with events when profiling is on.
+struct Timed {
+    vlasov_ctx *c;
+    int kid;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(vlasov_ctx *c_, int kid_) : c(c_), kid(kid_)
+    {
+        if (c->prof) {
+            a = take_event(c);
+            b = take_event(c);
+            if (a) (void)hipEventRecord(a, c->stream);
+        }
+    }
+    ~Timed()
+    {
+        if (c->prof && a && b) {
+            (void)hipEventRecord(b, c->stream);
+            c->recs.push_back({kid, a, b});
+        }
+    }
+};
+
+int check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VLASOV_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return VLASOV_OK;
+}
+
+template <typename T>
+int launch_drift(vlasov_ctx *c, int npass, bool partials)
+{
+    const vlasov_params &P = c->P;
+    dim3 grid((unsigned)((P.nx + DRIFT_TW - 1) / DRIFT_TW), (unsigned)c->nblk);
+    const T *fin = (const T *)c->fcur();
+    T *fout = (T *)c->fnext();
+    const int32_t *dm = c->at<int32_t>(c->L.drift_m);
+    const double4 *dw = c->at<double4>(c->L.drift_w);
+    double *part = c->at<double>(c->L.part);
+    const int nx = (int)P.nx, np = (int)P.np;
+    Timed tm(c, npass == 2 ? VLASOV_K_DRIFT2 : VLASOV_K_DRIFT);
+#define DRIFT_LAUNCH(NP, BC, PT) \
+    vk::k_drift<T, NP, BC, PT, DRIFT_TW><<<grid, DRIFT_TW, 0, c->stream>>>(fin, fout, dm, dw, part, nx, np)
+    if (P.bc_x == VLASOV_BC_PERIODIC) {
+        if (npass == 2) {
+            if (partials) DRIFT_LAUNCH(2, vk::BC_PERIODIC, true); else DRIFT_LAUNCH(2, vk::BC_PERIODIC, false);
+        } else {
+            if (partials) DRIFT_LAUNCH(1, vk::BC_PERIODIC, true); else DRIFT_LAUNCH(1, vk::BC_PERIODIC, false);
+        }
+    } else {
+        if (npass == 2) {
+            if (partials) DRIFT_LAUNCH(2, vk::BC_ZERO, true); else DRIFT_LAUNCH(2, vk::BC_ZERO, false);
+        } else {
+            if (partials) DRIFT_LAUNCH(1, vk::BC_ZERO, true); else DRIFT_LAUNCH(1, vk::BC_ZERO, false);
+        }
+    }
+#undef DRIFT_LAUNCH
+    int rc = check_launch("drift");
+    if (rc == VLASOV_OK) c->cur ^= 1;
+    return rc;
+}
+
+int drift(vlasov_ctx *c, int npass, bool partials)
+{
+    return c->P.storage == VLASOV_F32 ? launch_drift<float>(c, npass, partials)
+                                      : launch_drift<double>(c, npass, partials);
+}
+
+// Density from the partial sums, then the model force (and magnetization).
+int density_force(vlasov_ctx *c)
+{
+    const vlasov_params &P = c->P;
+    const int nx = (int)P.nx;
+    double *rho = c->at<double>(c->L.rho);
+    double *F = c->at<double>(c->L.F);
+    {
+        Timed tm(c, VLASOV_K_DENSITY);
+        vk::k_density<<<(nx + 3) / 4, 256, 0, c->stream>>>(c->at<double>(c->L.part), rho, nx, (int)c->nblk, c->dp);
+    }
+    int rc = check_launch("density");
+    if (rc) return rc;
+    double *hist = c->at<double>(c->L.hist);
+    int64_t *hcount = c->at<int64_t>(c->L.hcount);
+    double *mxmy = c->at<double>(c->L.mxmy);
+    const double *cs = c->at<double>(c->L.cs), *sn = c->at<double>(c->L.sn);
+    Timed tm(c, VLASOV_K_FORCE);
+    switch (P.model) {
+    case VLASOV_MODEL_HMF:
+        vk::k_force_hmf<<<1, 256, 0, c->stream>>>(rho, cs, sn, F, nx, c->dx, mxmy, hist, hcount, P.hist_cap);
+        break;
+    case VLASOV_MODEL_RING:
+        vk::k_magnetization<<<1, 64, 0, c->stream>>>(rho, cs, sn, nx, c->dx, mxmy, hist, hcount, P.hist_cap);
+        vk::k_force_ring<<<(nx + 3) / 4, 256, 0, c->stream>>>(rho, c->at<double>(c->L.ringK), F, nx, c->dx);
+        break;
+    case VLASOV_MODEL_SHEET: {
+        const double K = ((2.0 * M_PI) * P.sheet_G) * c->dx;
+        vk::k_force_sheet<<<1, 64, 0, c->stream>>>(rho, F, nx, K);
+        break;
+    }
+    default:
+        (void)hipMemcpyAsync(F, c->at<double>(c->L.Fext), (size_t)nx * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream);
+        break;
+    }
+    rc = check_launch("force");
+    if (rc == VLASOV_OK) c->have_force = true;
+    return rc;
+}
+
+template <typename T>
+int launch_kick(vlasov_ctx *c)
+{
+    const vlasov_params &P = c->P;
+    dim3 grid((unsigned)((P.nx + 255) / 256), (unsigned)((P.np + KICK_R - 1) / KICK_R));
+    const T *fin = (const T *)c->fcur();
+    T *fout = (T *)c->fnext();
+    const double *F = c->at<double>(c->L.F);
+    {
+        Timed tm(c, VLASOV_K_KICK);
+        if (P.bc_p == VLASOV_BC_PERIODIC)
+            vk::k_kick<T, vk::BC_PERIODIC, KICK_R><<<grid, 256, 0, c->stream>>>(fin, fout, F, P.dt, c->dp, (int)P.nx,
+                                                                             (int)P.np);
+        else
+            vk::k_kick<T, vk::BC_ZERO, KICK_R><<<grid, 256, 0, c->stream>>>(fin, fout, F, P.dt, c->dp, (int)P.nx,
+                                                                         (int)P.np);
+    }
+    int rc = check_launch("kick");
+    if (rc == VLASOV_OK) c->cur ^= 1;
+    return rc;
+}
+
+int kick(vlasov_ctx *c)
+{
+    return c->P.storage == VLASOV_F32 ? launch_kick<float>(c) : launch_kick<double>(c);
+}
+
+void to_host_f(const vlasov_ctx *c, const void *src, double *dst)
+{
+    const size_t N = (size_t)c->P.nx * (size_t)c->P.np;
+    if (c->P.storage == VLASOV_F32) {
+        const float *s = (const float *)src;
+        for (size_t k = 0; k < N; ++k) dst[k] = (double)s[k];
+    } else {
+        memcpy(dst, src, N * sizeof(double));
+    }
+}
+
+int upload_f(vlasov_ctx *c, const double *f_host)
+{
+    const size_t N = (size_t)c->P.nx * (size_t)c->P.np;
+    if (c->P.storage == VLASOV_F32) {
+        std::vector<float> tmp(N);
+        for (size_t k = 0; k < N; ++k) tmp[k] = (float)f_host[k];
+        HIP_TRY(hipMemcpyAsync(c->fcur(), tmp.data(), N * sizeof(float), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    } else {
+        HIP_TRY(hipMemcpyAsync(c->fcur(), f_host, N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    return VLASOV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *vlasov_last_error(void) { return g_err.c_str(); }
+
+size_t vlasov_f_bytes(const vlasov_params *p)
+{
+    if (!validate(p).empty()) return 0;
+    return 2 * (size_t)p->nx * (size_t)p->np * (p->storage == VLASOV_F32 ? 4 : 8);
+}
+
+size_t vlasov_workspace_bytes(const vlasov_params *p)
+{
+    if (!validate(p).empty()) return 0;
+    return layout_of(*p).total;
+}
+
+int vlasov_init(const vlasov_params *p, const double *f0_host, void *f_dev, void *ws_dev, void *hip_stream,
+                vlasov_ctx **out)
+{
+    std::string why = validate(p);
+    if (!why.empty()) return fail(VLASOV_E_INVAL, why);
+    if (!f0_host || !f_dev || !ws_dev || !out) return fail(VLASOV_E_INVAL, "NULL pointer argument");
+    if (((uintptr_t)f_dev % ALIGN) || ((uintptr_t)ws_dev % ALIGN))
+        return fail(VLASOV_E_INVAL, "device buffers must be 256-byte aligned");
+    vlasov_ctx *c = new vlasov_ctx();
+    c->P = *p;
+    c->stream = (hipStream_t)hip_stream;
+    c->s = p->storage == VLASOV_F32 ? 4 : 8;
+    const size_t N = (size_t)p->nx * (size_t)p->np;
+    c->f[0] = (char *)f_dev;
+    c->f[1] = (char *)f_dev + N * c->s;
+    c->cur = 0;
+    c->ws = (char *)ws_dev;
+    c->L = layout_of(*p);
+    c->dx = (p->xmax - p->xmin) / (double)p->nx;
+    c->dp = (p->pmax - p->pmin) / (double)p->np;
+    c->nblk = nblocks(p->np);
+    c->have_force = false;
+    c->prof = false;
+    for (int k = 0; k < VLASOV_K_COUNT; ++k) {
+        c->ms[k] = 0.0;
+        c->cnt[k] = 0;
+    }
+
+    // Drift line tables (eqs. step1, step4): row j moves by p_j (dt/2) / dx.
+    const double tau = 0.5 * p->dt;
+    c->h_dm.resize((size_t)p->np);
+    c->h_dw.resize((size_t)p->np);
+    for (int64_t j = 0; j < p->np; ++j) {
+        const double pj = p->pmin + (double)j * c->dp;
+        const vk::Foot ft = vk::foot_of_shift((pj * tau) / c->dx);
+        c->h_dm[j] = vk::reduce_offset(ft.m, p->nx, p->bc_x);
+        c->h_dw[j] = make_double4(ft.a, ft.b, ft.g, ft.d);
+    }
+    // Model tables.
+    std::vector<double> cs((size_t)p->nx), sn((size_t)p->nx), K((size_t)p->nx, 0.0), V((size_t)p->nx, 0.0);
+    for (int64_t i = 0; i < p->nx; ++i) {
+        const double th = p->xmin + (double)i * c->dx;
+        cs[i] = cos(th);
+        sn[i] = sin(th);
+    }
+    if (p->model == VLASOV_MODEL_RING) {
+        // eq. (ringpot): V(d) = -1/sqrt(q), V'(d) = sin d / (q sqrt q),
+        // q = 2 (1 + eps - cos d); V' made exactly odd, V exactly even.
+        const int64_t n = p->nx;
+        auto dV = [&](double d) {
+            const double q = 2.0 * ((1.0 + p->ring_eps) - cos(d));
+            return sin(d) / (q * sqrt(q));
+        };
+        auto Vd = [&](double d) {
+            const double q = 2.0 * ((1.0 + p->ring_eps) - cos(d));
+            return -1.0 / sqrt(q);
+        };
+        for (int64_t s = 0; s < n; ++s) {
+            if (s == 0 || 2 * s == n)
+                K[s] = 0.0;
+            else if (2 * s < n)
+                K[s] = dV((double)s * c->dx);
+            else
+                K[s] = -dV((double)(n - s) * c->dx);
+            const int64_t e = (2 * s > n) ? n - s : s;
+            V[s] = Vd((double)e * c->dx);
+        }
+    }
+    const size_t nxb = (size_t)p->nx * sizeof(double);
+    auto cleanup_fail = [&](int rc) {
+        delete c;
+        return rc;
+    };
+    int rc = VLASOV_OK;
+    const struct {
+        size_t off;
+        const void *src;
+        size_t bytes;
+    } ups[] = {{c->L.drift_m, c->h_dm.data(), (size_t)p->np * sizeof(int32_t)},
+               {c->L.drift_w, c->h_dw.data(), (size_t)p->np * sizeof(double4)},
+               {c->L.cs, cs.data(), nxb},
+               {c->L.sn, sn.data(), nxb},
+               {c->L.ringK, K.data(), nxb},
+               {c->L.ringV, V.data(), nxb}};
+    for (const auto &u : ups) {
+        hipError_t e = hipMemcpyAsync(c->ws + u.off, u.src, u.bytes, hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return cleanup_fail(fail(VLASOV_E_HIP, std::string("table upload: ") + hipGetErrorString(e)));
+    }
+    if (hipMemsetAsync(c->ws + c->L.Fext, 0, nxb, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->ws + c->L.hcount, 0, sizeof(int64_t), c->stream) != hipSuccess ||
+        hipMemsetAsync(c->ws + c->L.mxmy, 0, 2 * sizeof(double), c->stream) != hipSuccess)
+        return cleanup_fail(fail(VLASOV_E_HIP, "workspace clear failed"));
+    if ((rc = upload_f(c, f0_host)) != VLASOV_OK) return cleanup_fail(rc);
+    *out = c;
+    return VLASOV_OK;
+}
+
+int vlasov_set_external_force(vlasov_ctx *c, const double *F_host)
+{
+    if (!c || !F_host) return fail(VLASOV_E_INVAL, "NULL argument");
+    if (c->P.model != VLASOV_MODEL_EXTERNAL) return fail(VLASOV_E_STATE, "not an EXTERNAL-force context");
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.Fext, F_host, (size_t)c->P.nx * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return VLASOV_OK;
+}
+
+int vlasov_step(vlasov_ctx *c, int64_t nsteps)
+{
+    if (!c) return fail(VLASOV_E_INVAL, "NULL context");
+    if (nsteps < 0) return fail(VLASOV_E_INVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return VLASOV_OK;
+    int rc = drift(c, 1, true);  // step 1 of the first step
+    for (int64_t s = 0; rc == VLASOV_OK && s < nsteps; ++s) {
+        rc = density_force(c);                                     // step 2
+        if (rc == VLASOV_OK) rc = kick(c);                         // step 3
+        if (rc == VLASOV_OK) rc = drift(c, s + 1 < nsteps ? 2 : 1, s + 1 < nsteps);  // step 4 (+ next step 1)
+    }
+    return rc;
+}
+
+int vlasov_drift(vlasov_ctx *c, int32_t npass)
+{
+    if (!c) return fail(VLASOV_E_INVAL, "NULL context");
+    if (npass != 1 && npass != 2) return fail(VLASOV_E_INVAL, "npass must be 1 or 2");
+    return drift(c, npass, true);
+}
+
+int vlasov_force(vlasov_ctx *c, double *F_host, double *mxmy_host)
+{
+    if (!c) return fail(VLASOV_E_INVAL, "NULL context");
+    // density partial sums of the current f: reuse the diagnostic block pass
+    const vlasov_params &P = c->P;
+    dim3 grid((unsigned)((P.nx + 255) / 256), (unsigned)c->nblk);
+    double *scratch = (double *)c->fnext();
+    if (P.storage == VLASOV_F32)
+        vk::k_mom_blocks<float><<<grid, 256, 0, c->stream>>>((const float *)c->fcur(), scratch, (int)P.nx, (int)P.np,
+                                                             (int)c->nblk, P.pmin, c->dp);
+    else
+        vk::k_mom_blocks<double><<<grid, 256, 0, c->stream>>>((const double *)c->fcur(), scratch, (int)P.nx,
+                                                              (int)P.np, (int)c->nblk, P.pmin, c->dp);
+    int rc = check_launch("force: block sums");
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.part, scratch, (size_t)c->nblk * (size_t)P.nx * sizeof(double),
+                           hipMemcpyDeviceToDevice, c->stream));
+    if ((rc = density_force(c)) != VLASOV_OK) return rc;
+    if (F_host || mxmy_host) {
+        if (F_host)
+            HIP_TRY(hipMemcpyAsync(F_host, c->ws + c->L.F, (size_t)P.nx * sizeof(double), hipMemcpyDeviceToHost,
+                                   c->stream));
+        double mm[2] = {0.0, 0.0};
+        if (mxmy_host && (P.model == VLASOV_MODEL_HMF || P.model == VLASOV_MODEL_RING))
+            HIP_TRY(hipMemcpyAsync(mm, c->ws + c->L.mxmy, sizeof mm, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        if (mxmy_host) {
+            mxmy_host[0] = mm[0];
+            mxmy_host[1] = mm[1];
+        }
+    }
+    return VLASOV_OK;
+}
+
+int vlasov_kick(vlasov_ctx *c)
+{
+    if (!c) return fail(VLASOV_E_INVAL, "NULL context");
+    if (!c->have_force) return fail(VLASOV_E_STATE, "no force computed yet");
+    return kick(c);
+}
+
+int vlasov_moments(vlasov_ctx *c, vlasov_moments_t *out)
+{
+    if (!c || !out) return fail(VLASOV_E_INVAL, "NULL argument");
+    const vlasov_params &P = c->P;
+    const int nx = (int)P.nx;
+    double *scratch = (double *)c->fnext();  // the idle buffer of the pair
+    double *col = c->at<double>(c->L.mom_col);
+    double *phi = c->at<double>(c->L.mom_phi);
+    double *res = c->at<double>(c->L.mom_out);
+    {
+        Timed tm(c, VLASOV_K_MOMENTS);
+        dim3 grid((unsigned)((P.nx + 255) / 256), (unsigned)c->nblk);
+        if (P.storage == VLASOV_F32)
+            vk::k_mom_blocks<float><<<grid, 256, 0, c->stream>>>((const float *)c->fcur(), scratch, nx, (int)P.np,
+                                                                 (int)c->nblk, P.pmin, c->dp);
+        else
+            vk::k_mom_blocks<double><<<grid, 256, 0, c->stream>>>((const double *)c->fcur(), scratch, nx,
+                                                                  (int)P.np, (int)c->nblk, P.pmin, c->dp);
+        vk::k_mom_cols<<<(nx + 3) / 4, 256, 0, c->stream>>>(scratch, col, nx, (int)c->nblk, c->dp);
+        double wcoef = 0.0;
+        if (P.model == VLASOV_MODEL_RING) {
+            vk::k_mom_phi<true><<<(nx + 3) / 4, 256, 0, c->stream>>>(col, c->at<double>(c->L.ringV), phi, nx);
+            wcoef = (0.5 * c->dx) * c->dx;
+        } else if (P.model == VLASOV_MODEL_SHEET) {
+            vk::k_mom_phi<false><<<(nx + 3) / 4, 256, 0, c->stream>>>(col, nullptr, phi, nx);
+            wcoef = (((M_PI * P.sheet_G) * c->dx) * c->dx) * c->dx;
+        }
+        vk::k_mom_final<<<1, 64, 0, c->stream>>>(col, phi, c->at<double>(c->L.cs), c->at<double>(c->L.sn), res, nx,
+                                                 c->dx, P.model, wcoef);
+    }
+    int rc = check_launch("moments");
+    if (rc) return rc;
+    double h[8];
+    HIP_TRY(hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    out->mass = h[0];
+    out->momentum = h[1];
+    out->kinetic = h[2];
+    out->potential = h[3];
+    out->energy = h[4];
+    out->mx = h[5];
+    out->my = h[6];
+    out->l2 = h[7];
+    for (double v : h)
+        if (!isfinite(v)) return fail(VLASOV_E_NONFINITE, "non-finite diagnostic");
+    return VLASOV_OK;
+}
+
+int vlasov_mag_history(vlasov_ctx *c, double *mx, double *my, int64_t cap, int64_t *count)
+{
+    if (!c || !count || cap < 0 || (cap > 0 && (!mx || !my))) return fail(VLASOV_E_INVAL, "bad argument");
+    int64_t n = 0;
+    HIP_TRY(hipMemcpyAsync(&n, c->ws + c->L.hcount, sizeof n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    int64_t k = n < cap ? n : cap;
+    if (k > c->P.hist_cap) k = c->P.hist_cap;
+    if (k > 0) {
+        std::vector<double> h((size_t)k * 2);
+        HIP_TRY(hipMemcpyAsync(h.data(), c->ws + c->L.hist, (size_t)k * 2 * sizeof(double), hipMemcpyDeviceToHost,
+                               c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        for (int64_t t = 0; t < k; ++t) {
+            mx[t] = h[2 * t];
+            my[t] = h[2 * t + 1];
+        }
+    }
+    *count = n;
+    return VLASOV_OK;
+}
+
+int vlasov_read_f(vlasov_ctx *c, double *f_host)
+{
+    if (!c || !f_host) return fail(VLASOV_E_INVAL, "NULL argument");
+    const size_t bytes = (size_t)c->P.nx * (size_t)c->P.np * c->s;
+    std::vector<char> tmp(bytes);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), c->fcur(), bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    to_host_f(c, tmp.data(), f_host);
+    return VLASOV_OK;
+}
+
+int vlasov_write_f(vlasov_ctx *c, const double *f_host)
+{
+    if (!c || !f_host) return fail(VLASOV_E_INVAL, "NULL argument");
+    return upload_f(c, f_host);
+}
+
+int vlasov_destroy(vlasov_ctx *c)
+{
+    if (!c) return VLASOV_OK;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &r : c->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : c->pool) (void)hipEventDestroy(e);
+    delete c;
+    return VLASOV_OK;
+}
+
+int vlasov_profile_enable(vlasov_ctx *c, int32_t on)
+{
+    if (!c) return fail(VLASOV_E_INVAL, "NULL context");
+    if (on && !c->prof) {
+        for (int k = 0; k < VLASOV_K_COUNT; ++k) {
+            c->ms[k] = 0.0;
+            c->cnt[k] = 0;
+        }
+    }
+    c->prof = on != 0;
+    return VLASOV_OK;
+}
+
+int vlasov_profile_read(vlasov_ctx *c, int32_t kernel, double *total_ms, int64_t *launches)
+{
+    if (!c || kernel < 0 || kernel >= VLASOV_K_COUNT) return fail(VLASOV_E_INVAL, "bad argument");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (auto &r : c->recs) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        c->ms[r.kid] += ms;
+        c->cnt[r.kid] += 1;
+        c->pool.push_back(r.a);
+        c->pool.push_back(r.b);
+    }
+    c->recs.clear();
+    if (total_ms) *total_ms = c->ms[kernel];
+    if (launches) *launches = c->cnt[kernel];
+    return VLASOV_OK;
+}
+
+const char *vlasov_kernel_name(int32_t kernel)
+{
+    static const char *names[VLASOV_K_COUNT] = {"drift", "drift2", "density", "force", "kick", "moments"};
+    return (kernel >= 0 && kernel < VLASOV_K_COUNT) ? names[kernel] : "";
+}
+
+int vlasov_device_copy(void *dst, const void *src, size_t bytes, void *hip_stream)
+{
+    if (!dst || !src || (bytes % 16)) return fail(VLASOV_E_INVAL, "bad copy arguments");
+    const size_t n = bytes / 16;
+    if (n == 0) return VLASOV_OK;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    vk::k_copy<<<(unsigned)blocks, 256, 0, (hipStream_t)hip_stream>>>((const double2 *)src, (double2 *)dst, n);
+    return check_launch("copy");
+}
+
+}  // extern "C"

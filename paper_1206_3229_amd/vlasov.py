@@ -1,0 +1,215 @@
+"""Python binding of libvlasov.so (include/vlasov.h): argument marshalling only.
+
+Device memory comes from torch (the f pair and the workspace are uint8
+tensors on the GPU) and the stream is torch's current stream; every step of
+the solver runs in the library's HIP kernels.  There is no fallback: if the
+library is not built, or no GPU is present, construction fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libvlasov.so")
+
+OK, PENDING = 0, 1
+E_INVAL, E_NOMEM, E_HIP, E_STATE, E_NOTFOUND, E_NONFINITE = -1, -2, -3, -4, -5, -6
+
+K_DRIFT, K_DRIFT2, K_DENSITY, K_FORCE, K_KICK, K_MOMENTS = range(6)
+KERNELS = ("drift", "drift2", "density", "force", "kick", "moments")
+
+
+class VlasovError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"vlasov error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("model", C.c_int32), ("storage", C.c_int32), ("bc_x", C.c_int32), ("bc_p", C.c_int32),
+                ("nx", C.c_int64), ("np", C.c_int64),
+                ("xmin", C.c_double), ("xmax", C.c_double), ("pmin", C.c_double), ("pmax", C.c_double),
+                ("dt", C.c_double), ("ring_eps", C.c_double), ("sheet_G", C.c_double),
+                ("hist_cap", C.c_int64)]
+
+
+class Moments(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("mass", "momentum", "kinetic", "potential", "energy", "mx", "my", "l2")]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_D = C.POINTER(C.c_double)
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load the in-tree HIP library (built by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                              "(python -c 'import __graft_entry__ as g; g.build()')")
+        lib = C.CDLL(LIB_PATH)
+        P = C.POINTER(Params)
+        V = C.c_void_p
+        sig = {
+            "vlasov_f_bytes": (C.c_size_t, [P]),
+            "vlasov_workspace_bytes": (C.c_size_t, [P]),
+            "vlasov_init": (C.c_int, [P, _D, V, V, V, C.POINTER(V)]),
+            "vlasov_set_external_force": (C.c_int, [V, _D]),
+            "vlasov_step": (C.c_int, [V, C.c_int64]),
+            "vlasov_drift": (C.c_int, [V, C.c_int32]),
+            "vlasov_force": (C.c_int, [V, _D, _D]),
+            "vlasov_kick": (C.c_int, [V]),
+            "vlasov_moments": (C.c_int, [V, C.POINTER(Moments)]),
+            "vlasov_mag_history": (C.c_int, [V, _D, _D, C.c_int64, C.POINTER(C.c_int64)]),
+            "vlasov_read_f": (C.c_int, [V, _D]),
+            "vlasov_write_f": (C.c_int, [V, _D]),
+            "vlasov_destroy": (C.c_int, [V]),
+            "vlasov_last_error": (C.c_char_p, []),
+            "vlasov_profile_enable": (C.c_int, [V, C.c_int32]),
+            "vlasov_profile_read": (C.c_int, [V, C.c_int32, _D, C.POINTER(C.c_int64)]),
+            "vlasov_kernel_name": (C.c_char_p, [C.c_int32]),
+            "vlasov_device_copy": (C.c_int, [V, V, C.c_size_t, V]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def check(rc: int) -> int:
+    if rc < 0:
+        raise VlasovError(rc, load().vlasov_last_error().decode())
+    return rc
+
+
+def to_params(p, hist_cap: int = 0) -> Params:
+    """From paper_1206_3229_amd.inputs.Params."""
+    return Params(int(p.model), int(p.storage), int(p.bc_x), int(p.bc_p), int(p.nx), int(p.np_),
+                  float(p.xmin), float(p.xmax), float(p.pmin), float(p.pmax), float(p.dt),
+                  float(p.ring_eps), float(p.sheet_G), int(hist_cap))
+
+
+def _dptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_D)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the Vlasov solver runs only on the device")
+    return torch
+
+
+class Solver:
+    """One simulation: f pair and workspace in device memory, steps on the current stream."""
+
+    def __init__(self, params, f0: np.ndarray, hist_cap: int = 0, device: int | None = None):
+        torch = _torch()
+        lib = load()
+        self.params = params
+        self._p = to_params(params, hist_cap)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        fb = lib.vlasov_f_bytes(C.byref(self._p))
+        wb = lib.vlasov_workspace_bytes(C.byref(self._p))
+        if fb == 0 or wb == 0:
+            raise VlasovError(E_INVAL, "invalid parameters")
+        with torch.cuda.device(self.device):
+            self.f_buf = torch.empty(fb, dtype=torch.uint8, device=self.device)
+            self.ws_buf = torch.empty(wb, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+        f0 = np.ascontiguousarray(f0, dtype=np.float64)
+        if f0.shape != (params.np_, params.nx):
+            raise ValueError(f"f0 shape {f0.shape} != (np, nx) = {(params.np_, params.nx)}")
+        ctx = C.c_void_p()
+        check(lib.vlasov_init(C.byref(self._p), _dptr(f0), C.c_void_p(self.f_buf.data_ptr()),
+                              C.c_void_p(self.ws_buf.data_ptr()), C.c_void_p(self.stream.cuda_stream),
+                              C.byref(ctx)))
+        self._ctx = ctx
+        self.nx, self.np_ = params.nx, params.np_
+
+    # -- steps -----------------------------------------------------------
+    def step(self, nsteps: int = 1):
+        check(load().vlasov_step(self._ctx, int(nsteps)))
+
+    def drift(self, npass: int = 1):
+        check(load().vlasov_drift(self._ctx, int(npass)))
+
+    def force(self):
+        F = np.empty(self.nx)
+        mm = np.zeros(2)
+        check(load().vlasov_force(self._ctx, _dptr(F), _dptr(mm)))
+        return F, (float(mm[0]), float(mm[1]))
+
+    def kick(self):
+        check(load().vlasov_kick(self._ctx))
+
+    def set_external_force(self, F: np.ndarray):
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        assert F.shape == (self.nx,)
+        check(load().vlasov_set_external_force(self._ctx, _dptr(F)))
+
+    # -- state -----------------------------------------------------------
+    def read_f(self) -> np.ndarray:
+        out = np.empty((self.np_, self.nx))
+        check(load().vlasov_read_f(self._ctx, _dptr(out)))
+        return out
+
+    def write_f(self, f: np.ndarray):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        assert f.shape == (self.np_, self.nx)
+        check(load().vlasov_write_f(self._ctx, _dptr(f)))
+
+    def moments(self) -> dict:
+        m = Moments()
+        check(load().vlasov_moments(self._ctx, C.byref(m)))
+        return m.as_dict()
+
+    def mag_history(self) -> np.ndarray:
+        cap = self._p.hist_cap
+        mx, my = np.zeros(max(cap, 1)), np.zeros(max(cap, 1))
+        n = C.c_int64()
+        check(load().vlasov_mag_history(self._ctx, _dptr(mx), _dptr(my), cap, C.byref(n)))
+        k = min(n.value, cap)
+        return np.stack([mx[:k], my[:k]], axis=1)
+
+    # -- measurement -----------------------------------------------------
+    def profile(self, on: bool = True):
+        check(load().vlasov_profile_enable(self._ctx, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        out = {}
+        for k, name in enumerate(KERNELS):
+            ms = C.c_double()
+            n = C.c_int64()
+            check(load().vlasov_profile_read(self._ctx, k, C.byref(ms), C.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            load().vlasov_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def device_copy(dst, src, nbytes: int, stream=None):
+    """Library streaming copy between two device tensors (bandwidth ceiling)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    check(load().vlasov_device_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), int(nbytes),
+                                    C.c_void_p(s.cuda_stream)))

@@ -1,0 +1,83 @@
+"""The C ABI library loads and exports every entry point declared in
+include/vlasov.h; host-side parameter validation (no GPU needed)."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vlasov.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vlasov_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1206_3229_amd import vlasov as V
+    return V.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("vlasov_init", "vlasov_step", "vlasov_moments", "vlasov_destroy", "vlasov_last_error"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def _params(**kw):
+    from paper_1206_3229_amd import vlasov as V
+    d = dict(model=0, storage=0, bc_x=0, bc_p=0, nx=64, np=32, xmin=-math.pi, xmax=math.pi, pmin=-2.0, pmax=2.0,
+             dt=0.1, ring_eps=0.01, sheet_G=1.0, hist_cap=10)
+    d.update(kw)
+    return V.Params(*[d[n] for n, _ in V.Params._fields_])
+
+
+def test_buffer_sizes(lib):
+    p = _params()
+    assert lib.vlasov_f_bytes(C.byref(p)) == 2 * 64 * 32 * 8
+    p32 = _params(storage=1)
+    assert lib.vlasov_f_bytes(C.byref(p32)) == 2 * 64 * 32 * 4
+    ws = lib.vlasov_workspace_bytes(C.byref(p))
+    # at least the density partial sums (2 blocks of 16 rows) and the tables
+    assert ws >= 2 * 64 * 8 + 32 * 40 + 6 * 64 * 8
+    assert ws % 256 == 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=8), dict(np=15), dict(model=7), dict(storage=3), dict(bc_x=2), dict(xmax=-4.0),
+    dict(dt=0.0), dict(dt=float("nan")), dict(pmin=float("inf")), dict(model=0, bc_x=1),
+    dict(model=1, ring_eps=0.0), dict(hist_cap=-1), dict(nx=1 << 16, np=1 << 16),
+])
+def test_invalid_parameters_rejected_on_host(lib, bad):
+    p = _params(**bad)
+    assert lib.vlasov_f_bytes(C.byref(p)) == 0
+    assert lib.vlasov_workspace_bytes(C.byref(p)) == 0
+    ctx = C.c_void_p()
+    f0 = (C.c_double * 16)()
+    rc = lib.vlasov_init(C.byref(p), f0, C.c_void_p(256), C.c_void_p(512), None, C.byref(ctx))
+    assert rc == -1
+    assert lib.vlasov_last_error().decode() != ""
+
+
+def test_null_and_misaligned_pointers_rejected(lib):
+    p = _params()
+    ctx = C.c_void_p()
+    f0 = (C.c_double * (64 * 32))()
+    assert lib.vlasov_init(C.byref(p), None, C.c_void_p(256), C.c_void_p(512), None, C.byref(ctx)) == -1
+    assert lib.vlasov_init(C.byref(p), f0, C.c_void_p(260), C.c_void_p(512), None, C.byref(ctx)) == -1
+    assert "aligned" in lib.vlasov_last_error().decode()
+
+
+def test_kernel_names(lib):
+    assert [lib.vlasov_kernel_name(k).decode() for k in range(6)] == \
+        ["drift", "drift2", "density", "force", "kick", "moments"]
