@@ -5,6 +5,7 @@
 // x drift (constant over a run) and the model tables (sin/cos of the angle
 // nodes, ring-potential derivative and value) with the host libm and uploads
 // them once; no transcendental function is evaluated on the device.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -36,8 +37,8 @@ int fail(int code, const std::string &msg)
 constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
-constexpr int DRIFT_TW = 256;
-constexpr int KICK_R = 16;
+constexpr int DRIFT_NT = 128;  // threads per drift workgroup (2 columns each)
+constexpr int KICK_R = 32;
 
 // Workspace layout (byte offsets, each 256-aligned).
 struct Layout {
@@ -144,27 +145,22 @@ hipEvent_t take_event(vlasov_ctx *c)
     return e;
 }
 
-// Brackets one launch with events when profiling is on.
-struct Timed {
-    vlasov_ctx *c;
-    int kid;
-    hipEvent_t a = nullptr, b = nullptr;
-    Timed(vlasov_ctx *c_, int kid_) : c(c_), kid(kid_)
-    {
-        if (c->prof) {
-            a = take_event(c);
-            b = take_event(c);
-            if (a) (void)hipEventRecord(a, c->stream);
-        }
-    }
-    ~Timed()
-    {
-        if (c->prof && a && b) {
-            (void)hipEventRecord(b, c->stream);
+// Launches a kernel on the context's stream.  When profiling is on, the
+// launch carries its own start/stop events (recorded by the dispatch itself,
+// so no extra packets sit between consecutive kernels).
+template <typename... KArgs, typename... Args>
+void launch(vlasov_ctx *c, int kid, void (*kernel)(KArgs...), dim3 grid, dim3 block, Args... args)
+{
+    if (c->prof) {
+        hipEvent_t a = take_event(c), b = take_event(c);
+        if (a && b) {
+            hipExtLaunchKernelGGL(kernel, grid, block, 0, c->stream, a, b, 0, static_cast<KArgs>(args)...);
             c->recs.push_back({kid, a, b});
+            return;
         }
     }
-};
+    kernel<<<grid, block, 0, c->stream>>>(static_cast<KArgs>(args)...);
+}
 
 int check_launch(const char *what)
 {
@@ -177,16 +173,17 @@ template <typename T>
 int launch_drift(vlasov_ctx *c, int npass, bool partials)
 {
     const vlasov_params &P = c->P;
-    dim3 grid((unsigned)((P.nx + DRIFT_TW - 1) / DRIFT_TW), (unsigned)c->nblk);
+    const int ntx = (int)((P.nx + 2 * DRIFT_NT - 1) / (2 * DRIFT_NT)), nty = (int)c->nblk;
+    const dim3 grid((unsigned)vk::xcd_grid(ntx, nty));
     const T *fin = (const T *)c->fcur();
     T *fout = (T *)c->fnext();
     const int32_t *dm = c->at<int32_t>(c->L.drift_m);
     const double4 *dw = c->at<double4>(c->L.drift_w);
     double *part = c->at<double>(c->L.part);
     const int nx = (int)P.nx, np = (int)P.np;
-    Timed tm(c, npass == 2 ? VLASOV_K_DRIFT2 : VLASOV_K_DRIFT);
+    const int kid = npass == 2 ? VLASOV_K_DRIFT2 : VLASOV_K_DRIFT;
 #define DRIFT_LAUNCH(NP, BC, PT) \
-    vk::k_drift<T, NP, BC, PT, DRIFT_TW><<<grid, DRIFT_TW, 0, c->stream>>>(fin, fout, dm, dw, part, nx, np)
+    launch(c, kid, vk::k_drift<T, NP, BC, PT, DRIFT_NT>, grid, dim3(DRIFT_NT), fin, fout, dm, dw, part, nx, np, ntx, nty)
     if (P.bc_x == VLASOV_BC_PERIODIC) {
         if (npass == 2) {
             if (partials) DRIFT_LAUNCH(2, vk::BC_PERIODIC, true); else DRIFT_LAUNCH(2, vk::BC_PERIODIC, false);
@@ -212,6 +209,12 @@ int drift(vlasov_ctx *c, int npass, bool partials)
                                       : launch_drift<double>(c, npass, partials);
 }
 
+// Force array read by the kick: the caller's table for the EXTERNAL model.
+const double *force_ptr(const vlasov_ctx *c)
+{
+    return c->at<double>(c->P.model == VLASOV_MODEL_EXTERNAL ? c->L.Fext : c->L.F);
+}
+
 // Density from the partial sums, then the model force (and magnetization).
 int density_force(vlasov_ctx *c)
 {
@@ -219,34 +222,34 @@ int density_force(vlasov_ctx *c)
     const int nx = (int)P.nx;
     double *rho = c->at<double>(c->L.rho);
     double *F = c->at<double>(c->L.F);
-    {
-        Timed tm(c, VLASOV_K_DENSITY);
-        vk::k_density<<<(nx + 3) / 4, 256, 0, c->stream>>>(c->at<double>(c->L.part), rho, nx, (int)c->nblk, c->dp);
-    }
+    launch(c, VLASOV_K_DENSITY, vk::k_density, dim3((unsigned)((nx + 15) / 16)), dim3(256),
+           c->at<double>(c->L.part), rho, nx, (int)c->nblk, c->dp);
     int rc = check_launch("density");
     if (rc) return rc;
     double *hist = c->at<double>(c->L.hist);
     int64_t *hcount = c->at<int64_t>(c->L.hcount);
     double *mxmy = c->at<double>(c->L.mxmy);
     const double *cs = c->at<double>(c->L.cs), *sn = c->at<double>(c->L.sn);
-    Timed tm(c, VLASOV_K_FORCE);
+    const bool staged = nx <= vk::FORCE_LDS_MAX;
     switch (P.model) {
     case VLASOV_MODEL_HMF:
-        vk::k_force_hmf<<<1, 256, 0, c->stream>>>(rho, cs, sn, F, nx, c->dx, mxmy, hist, hcount, P.hist_cap);
+        launch(c, VLASOV_K_FORCE, staged ? vk::k_force_hmf<true> : vk::k_force_hmf<false>, dim3(1), dim3(1024), rho,
+               cs, sn, F, nx, c->dx, mxmy, hist, hcount, P.hist_cap);
         break;
     case VLASOV_MODEL_RING:
-        vk::k_magnetization<<<1, 64, 0, c->stream>>>(rho, cs, sn, nx, c->dx, mxmy, hist, hcount, P.hist_cap);
-        vk::k_force_ring<<<(nx + 3) / 4, 256, 0, c->stream>>>(rho, c->at<double>(c->L.ringK), F, nx, c->dx);
+        launch(c, VLASOV_K_FORCE, staged ? vk::k_magnetization<true> : vk::k_magnetization<false>, dim3(1),
+               dim3(1024), rho, cs, sn, nx, c->dx, mxmy, hist, hcount, P.hist_cap);
+        launch(c, VLASOV_K_FORCE, vk::k_force_ring, dim3((unsigned)((nx + 3) / 4)), dim3(256), rho,
+               c->at<double>(c->L.ringK), F, nx, c->dx);
         break;
     case VLASOV_MODEL_SHEET: {
         const double K = ((2.0 * M_PI) * P.sheet_G) * c->dx;
-        vk::k_force_sheet<<<1, 64, 0, c->stream>>>(rho, F, nx, K);
+        launch(c, VLASOV_K_FORCE, nx <= vk::SHEET_LDS_MAX ? vk::k_force_sheet<true> : vk::k_force_sheet<false>,
+               dim3(1), dim3(1024), rho, F, nx, K);
         break;
     }
     default:
-        (void)hipMemcpyAsync(F, c->at<double>(c->L.Fext), (size_t)nx * sizeof(double), hipMemcpyDeviceToDevice,
-                             c->stream);
-        break;
+        break;  // EXTERNAL: the kick reads the caller's force table
     }
     rc = check_launch("force");
     if (rc == VLASOV_OK) c->have_force = true;
@@ -257,19 +260,17 @@ template <typename T>
 int launch_kick(vlasov_ctx *c)
 {
     const vlasov_params &P = c->P;
-    dim3 grid((unsigned)((P.nx + 255) / 256), (unsigned)((P.np + KICK_R - 1) / KICK_R));
+    const int ntx = (int)((P.nx + 255) / 256), nty = (int)((P.np + KICK_R - 1) / KICK_R);
+    const dim3 grid((unsigned)vk::xcd_grid(ntx, nty));
     const T *fin = (const T *)c->fcur();
     T *fout = (T *)c->fnext();
-    const double *F = c->at<double>(c->L.F);
-    {
-        Timed tm(c, VLASOV_K_KICK);
-        if (P.bc_p == VLASOV_BC_PERIODIC)
-            vk::k_kick<T, vk::BC_PERIODIC, KICK_R><<<grid, 256, 0, c->stream>>>(fin, fout, F, P.dt, c->dp, (int)P.nx,
-                                                                             (int)P.np);
-        else
-            vk::k_kick<T, vk::BC_ZERO, KICK_R><<<grid, 256, 0, c->stream>>>(fin, fout, F, P.dt, c->dp, (int)P.nx,
-                                                                         (int)P.np);
-    }
+    const double *F = force_ptr(c);
+    if (P.bc_p == VLASOV_BC_PERIODIC)
+        launch(c, VLASOV_K_KICK, vk::k_kick<T, vk::BC_PERIODIC, KICK_R>, grid, dim3(256), fin, fout, F, P.dt, c->dp,
+               (int)P.nx, (int)P.np, ntx, nty);
+    else
+        launch(c, VLASOV_K_KICK, vk::k_kick<T, vk::BC_ZERO, KICK_R>, grid, dim3(256), fin, fout, F, P.dt, c->dp,
+               (int)P.nx, (int)P.np, ntx, nty);
     int rc = check_launch("kick");
     if (rc == VLASOV_OK) c->cur ^= 1;
     return rc;
@@ -472,7 +473,7 @@ int vlasov_force(vlasov_ctx *c, double *F_host, double *mxmy_host)
     if ((rc = density_force(c)) != VLASOV_OK) return rc;
     if (F_host || mxmy_host) {
         if (F_host)
-            HIP_TRY(hipMemcpyAsync(F_host, c->ws + c->L.F, (size_t)P.nx * sizeof(double), hipMemcpyDeviceToHost,
+            HIP_TRY(hipMemcpyAsync(F_host, force_ptr(c), (size_t)P.nx * sizeof(double), hipMemcpyDeviceToHost,
                                    c->stream));
         double mm[2] = {0.0, 0.0};
         if (mxmy_host && (P.model == VLASOV_MODEL_HMF || P.model == VLASOV_MODEL_RING))
@@ -502,27 +503,27 @@ int vlasov_moments(vlasov_ctx *c, vlasov_moments_t *out)
     double *col = c->at<double>(c->L.mom_col);
     double *phi = c->at<double>(c->L.mom_phi);
     double *res = c->at<double>(c->L.mom_out);
-    {
-        Timed tm(c, VLASOV_K_MOMENTS);
-        dim3 grid((unsigned)((P.nx + 255) / 256), (unsigned)c->nblk);
-        if (P.storage == VLASOV_F32)
-            vk::k_mom_blocks<float><<<grid, 256, 0, c->stream>>>((const float *)c->fcur(), scratch, nx, (int)P.np,
-                                                                 (int)c->nblk, P.pmin, c->dp);
-        else
-            vk::k_mom_blocks<double><<<grid, 256, 0, c->stream>>>((const double *)c->fcur(), scratch, nx,
-                                                                  (int)P.np, (int)c->nblk, P.pmin, c->dp);
-        vk::k_mom_cols<<<(nx + 3) / 4, 256, 0, c->stream>>>(scratch, col, nx, (int)c->nblk, c->dp);
-        double wcoef = 0.0;
-        if (P.model == VLASOV_MODEL_RING) {
-            vk::k_mom_phi<true><<<(nx + 3) / 4, 256, 0, c->stream>>>(col, c->at<double>(c->L.ringV), phi, nx);
-            wcoef = (0.5 * c->dx) * c->dx;
-        } else if (P.model == VLASOV_MODEL_SHEET) {
-            vk::k_mom_phi<false><<<(nx + 3) / 4, 256, 0, c->stream>>>(col, nullptr, phi, nx);
-            wcoef = (((M_PI * P.sheet_G) * c->dx) * c->dx) * c->dx;
-        }
-        vk::k_mom_final<<<1, 64, 0, c->stream>>>(col, phi, c->at<double>(c->L.cs), c->at<double>(c->L.sn), res, nx,
-                                                 c->dx, P.model, wcoef);
+    const dim3 grid((unsigned)((P.nx + 255) / 256), (unsigned)c->nblk);
+    if (P.storage == VLASOV_F32)
+        launch(c, VLASOV_K_MOMENTS, vk::k_mom_blocks<float>, grid, dim3(256), (const float *)c->fcur(), scratch, nx,
+               (int)P.np, (int)c->nblk, P.pmin, c->dp);
+    else
+        launch(c, VLASOV_K_MOMENTS, vk::k_mom_blocks<double>, grid, dim3(256), (const double *)c->fcur(), scratch, nx,
+               (int)P.np, (int)c->nblk, P.pmin, c->dp);
+    launch(c, VLASOV_K_MOMENTS, vk::k_mom_cols, dim3((unsigned)((nx + 3) / 4)), dim3(256), scratch, col, nx,
+           (int)c->nblk, c->dp);
+    double wcoef = 0.0;
+    if (P.model == VLASOV_MODEL_RING) {
+        launch(c, VLASOV_K_MOMENTS, vk::k_mom_phi<true>, dim3((unsigned)((nx + 3) / 4)), dim3(256), col,
+               c->at<double>(c->L.ringV), phi, nx);
+        wcoef = (0.5 * c->dx) * c->dx;
+    } else if (P.model == VLASOV_MODEL_SHEET) {
+        launch(c, VLASOV_K_MOMENTS, vk::k_mom_phi<false>, dim3((unsigned)((nx + 3) / 4)), dim3(256), col,
+               (const double *)nullptr, phi, nx);
+        wcoef = (((M_PI * P.sheet_G) * c->dx) * c->dx) * c->dx;
     }
+    launch(c, VLASOV_K_MOMENTS, vk::k_mom_final, dim3(1), dim3(64), col, phi, c->at<double>(c->L.cs),
+           c->at<double>(c->L.sn), res, nx, c->dx, (int)P.model, wcoef);
     int rc = check_launch("moments");
     if (rc) return rc;
     double h[8];
@@ -635,8 +636,8 @@ int vlasov_device_copy(void *dst, const void *src, size_t bytes, void *hip_strea
     if (!dst || !src || (bytes % 16)) return fail(VLASOV_E_INVAL, "bad copy arguments");
     const size_t n = bytes / 16;
     if (n == 0) return VLASOV_OK;
-    size_t blocks = (n + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
+    const size_t blocks = (n + 255) / 256;
+    if (blocks > 0xFFFFFFFFull) return fail(VLASOV_E_INVAL, "copy too large");
     vk::k_copy<<<(unsigned)blocks, 256, 0, (hipStream_t)hip_stream>>>((const double2 *)src, (double2 *)dst, n);
     return check_launch("copy");
 }

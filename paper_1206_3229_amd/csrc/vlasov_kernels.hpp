@@ -113,6 +113,15 @@ __device__ __forceinline__ int wrap(int q, int n)
     return r < 0 ? r + n : r;
 }
 
+// One sample of a line of n values (stride between samples `stride`) under
+// the boundary rule of the axis.
+template <typename T, int BC>
+__device__ __forceinline__ T sample(const T *__restrict__ line, int q, int n, size_t stride)
+{
+    if (BC == BC_PERIODIC) return line[(size_t)wrap(q, n) * stride];
+    return (q >= 0 && q < n) ? line[(size_t)q * stride] : T(0);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -120,127 +129,265 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Tile placement.  Workgroups are dispatched to the 8 XCDs of the chip in
+// round-robin order of their linear id; each XCD is given a contiguous band of
+// tile rows (x fastest inside the band) so that tiles sharing halo lines are
+// served by the same L2.  Launch 8 * ceil(nty/8) * ntx workgroups.
+constexpr int NXCD = 8;
+
+__host__ __device__ inline int xcd_grid(int ntx, int nty) { return NXCD * ((nty + NXCD - 1) / NXCD) * ntx; }
+
+__device__ __forceinline__ bool xcd_tile(int ntx, int nty, int &tx, int &ty)
+{
+    const int id = blockIdx.x;
+    const int k = id / NXCD;
+    const int per = (nty + NXCD - 1) / NXCD;
+    ty = (id % NXCD) * per + k / ntx;
+    tx = k % ntx;
+    return ty < nty;
+}
+
+// Two adjacent values as one 8- or 16-byte vector.
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+// Interpolates the two adjacent outputs q = 2u, 2u + 1 of a row from an LDS
+// window `src` (the sample of output q's cell start is src[q + 4]): three
+// stencils shared by the pair, read as six aligned pairs src[2u .. 2u + 11].
+template <typename T>
+__device__ __forceinline__ void spline_pair(const T *src, int u, T a, T b, T g, T d, T &o0, T &o1)
+{
+    using V2 = typename Vec2<T>::type;
+    const V2 *p = reinterpret_cast<const V2 *>(src) + u;
+    T x[12];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const V2 v = p[k];
+        x[2 * k] = v.x;
+        x[2 * k + 1] = v.y;
+    }
+    const T D0 = second_diff(x + 4), D1 = second_diff(x + 5), D2 = second_diff(x + 6);
+    o0 = spline(a, b, g, d, x[4], x[5], D0, D1);
+    o1 = spline(a, b, g, d, x[5], x[6], D1, D2);
+}
+
 // ---------------------------------------------------------------------------
 // Steps 1 and 4 (eqs. step1, step4): drift along x, row j shifted by the
 // constant p_j tau/dx cells.  NPASS = 2 applies the half drift twice (the
 // second half drift of one step and the first of the next), keeping the
-// intermediate row in LDS.  One workgroup: TW consecutive columns of 16
-// consecutive rows; the input window of each row is staged in LDS with its
-// halo (periodic wrap or zeros).  With PARTIALS, also writes the serial
-// column sum of the 16 output rows (density partial sums).
+// intermediate row in LDS.  One workgroup of NT threads: TW = 2 NT consecutive
+// columns of a block of 16 consecutive rows, two adjacent columns per thread.
+// Rows stream through two LDS window buffers; the window of each row (TW
+// columns plus the stencil and shift halo, periodic wrap or zeros) is
+// requested PF rows ahead of its use and held in registers meanwhile.  With
+// PARTIALS, also writes the serial column sum of the 16 output rows (density
+// partial sums).
 // ---------------------------------------------------------------------------
-template <typename T, int NPASS, int BC, bool PARTIALS, int TW>
-__global__ __launch_bounds__(TW) void k_drift(const T *__restrict__ fin, T *__restrict__ fout,
-                                              const int32_t *__restrict__ dm, const double4 *__restrict__ dw,
-                                              double *__restrict__ part, int nx, int np)
+template <typename T, int BC, int NPASS, int TW, int NT, int NLD>
+__device__ __forceinline__ void load_window(const T *__restrict__ fin, const int32_t *__restrict__ dm, int j, int i0,
+                                            int nx, T (&v)[NLD])
 {
     constexpr int WIN = TW + 9 * NPASS;
-    __shared__ T win[WIN];
-    __shared__ T mid[NPASS == 2 ? TW + 9 : 1];
-    const int t = threadIdx.x;
-    const int i0 = blockIdx.x * TW;
-    const int i = i0 + t;
-    const int j0 = blockIdx.y * ROWS_PER_BLOCK;
-    const int jend = min(j0 + ROWS_PER_BLOCK, np);
-    double acc = 0.0;
-    for (int j = j0; j < jend; ++j) {
-        const int m = dm[j];
-        const double4 w = dw[j];
-        const T a = (T)w.x, b = (T)w.y, g = (T)w.z, d = (T)w.w;
-        const T *row = fin + (size_t)j * nx;
-        // win[s] holds the sample at global position base + s
-        const int base = i0 + NPASS * m - 4 * NPASS;
-        for (int s = t; s < WIN; s += TW) {
-            const int q = base + s;
-            T v;
-            if (BC == BC_PERIODIC)
-                v = row[wrap(q, nx)];
-            else
-                v = (q >= 0 && q < nx) ? row[q] : T(0);
-            win[s] = v;
-        }
-        __syncthreads();
-        const T *src = win;
-        if (NPASS == 2) {
-            // first half drift at positions i0 + m - 4 + u, u in [0, TW + 9)
-            for (int u = t; u < TW + 9; u += TW) {
-                const T *x = win + u + 4;
-                T v = spline(a, b, g, d, x[0], x[1], second_diff(x), second_diff(x + 1));
-                if (BC == BC_ZERO) {
-                    const int q = i0 + m - 4 + u;
-                    if (q < 0 || q >= nx) v = T(0);
-                }
-                mid[u] = v;
+    const T *row = fin + (size_t)j * nx;
+    int base = i0 + NPASS * dm[j] - 4 * NPASS;
+    if (BC == BC_PERIODIC) base = wrap(base, nx);
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+        const int s = threadIdx.x + k * NT;
+        if (s < WIN) {
+            int q = base + s;
+            if (BC == BC_PERIODIC) {
+                if (q >= nx) q -= nx;
+                if (q >= nx) q = wrap(q, nx);
+                v[k] = row[q];
+            } else {
+                v[k] = (q >= 0 && q < nx) ? row[q] : T(0);
             }
-            __syncthreads();
-            src = mid;
         }
-        const T *x = src + t + 4;
-        const T v = spline(a, b, g, d, x[0], x[1], second_diff(x), second_diff(x + 1));
-        if (i < nx) {
-            fout[(size_t)j * nx + i] = v;
-            if (PARTIALS) acc = acc + (double)v;
-        }
-        __syncthreads();
     }
-    if (PARTIALS && i < nx) part[(size_t)blockIdx.y * nx + i] = acc;
+}
+
+template <typename T, int NPASS, int BC, bool PARTIALS, int NT>
+__global__ __launch_bounds__(NT) void k_drift(const T *__restrict__ fin, T *__restrict__ fout,
+                                              const int32_t *__restrict__ dm, const double4 *__restrict__ dw,
+                                              double *__restrict__ part, int nx, int np, int ntx, int nty)
+{
+    using V2 = typename Vec2<T>::type;
+    constexpr int R = ROWS_PER_BLOCK;
+    constexpr int PF = 4;                      // rows requested ahead
+    constexpr int TW = 2 * NT;
+    constexpr int WIN = TW + 9 * NPASS;        // window samples per row
+    constexpr int LDW = (WIN + 4) & ~1;        // even row pitch; pair reads run up to 2 past the window
+    constexpr int MIDN = TW + 9;               // first-pass outputs per row (NPASS = 2)
+    constexpr int NLD = (WIN + NT - 1) / NT;   // loads per thread per row
+    __shared__ __attribute__((aligned(16))) T win[2][LDW];
+    __shared__ __attribute__((aligned(16))) T mid[NPASS == 2 ? MIDN + 3 : 2];
+    int tx, ty;
+    if (!xcd_tile(ntx, nty, tx, ty)) return;
+    const int t = threadIdx.x;
+    const int i0 = tx * TW;
+    const int j0 = ty * R;
+    const int nr = min(R, np - j0);
+
+    if (t < LDW - WIN) {
+        win[0][WIN + t] = T(0);
+        win[1][WIN + t] = T(0);
+    }
+    if (NPASS == 2 && t < 3) mid[MIDN + t] = T(0);
+
+    T v[PF][NLD];
+#pragma unroll
+    for (int r = 0; r < PF; ++r)
+        if (r < nr) load_window<T, BC, NPASS, TW, NT, NLD>(fin, dm, j0 + r, i0, nx, v[r]);
+
+    const int i = i0 + 2 * t;  // first of this thread's two columns
+    double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (r < nr) {
+            T *wrow = win[r & 1];
+#pragma unroll
+            for (int k = 0; k < NLD; ++k) {
+                const int s = t + k * NT;
+                if (s < WIN) wrow[s] = v[r % PF][k];
+            }
+            if (r + PF < nr) load_window<T, BC, NPASS, TW, NT, NLD>(fin, dm, j0 + r + PF, i0, nx, v[r % PF]);
+            __syncthreads();
+            const int j = j0 + r;
+            const double4 w = dw[j];
+            const T a = (T)w.x, b = (T)w.y, g = (T)w.z, d = (T)w.w;
+            const T *src = wrow;
+            if (NPASS == 2) {
+                // first half drift at positions i0 + m - 4 + q, q in [0, TW + 9)
+                const int m = dm[j];
+                for (int u = t; 2 * u < MIDN; u += NT) {
+                    T o0, o1;
+                    spline_pair(src, u, a, b, g, d, o0, o1);
+                    if (BC == BC_ZERO) {
+                        const int q = i0 + m - 4 + 2 * u;
+                        if (q < 0 || q >= nx) o0 = T(0);
+                        if (q + 1 < 0 || q + 1 >= nx) o1 = T(0);
+                    }
+                    V2 o;
+                    o.x = o0;
+                    o.y = o1;
+                    reinterpret_cast<V2 *>(mid)[u] = o;
+                }
+                __syncthreads();
+                src = mid;
+            }
+            T o0, o1;
+            spline_pair(src, t, a, b, g, d, o0, o1);
+            T *orow = fout + (size_t)j * nx;
+            if (i + 1 < nx && (nx & 1) == 0) {
+                V2 o;
+                o.x = o0;
+                o.y = o1;
+                *reinterpret_cast<V2 *>(orow + i) = o;
+            } else {
+                if (i < nx) orow[i] = o0;
+                if (i + 1 < nx) orow[i + 1] = o1;
+            }
+            if (PARTIALS) {
+                acc0 = acc0 + (double)o0;
+                acc1 = acc1 + (double)o1;
+            }
+        }
+    }
+    if (PARTIALS) {
+        double *prow = part + (size_t)ty * nx;
+        if (i < nx) prow[i] = acc0;
+        if (i + 1 < nx) prow[i + 1] = acc1;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Step 3 (eq. step3): kick along p, column i shifted by F_i dt/dp cells.  One
 // thread per column and R consecutive output rows; the R + 9 samples of the
-// column window are held in registers (lanes of a wavefront read adjacent
-// columns of the same rows).
+// column window are requested at once and held in registers (the lanes of a
+// wavefront read adjacent columns of the same rows).
 // ---------------------------------------------------------------------------
 template <typename T, int BC, int R>
 __global__ __launch_bounds__(256) void k_kick(const T *__restrict__ fin, T *__restrict__ fout,
-                                              const double *__restrict__ F, double dt, double dp, int nx, int np)
+                                              const double *__restrict__ F, double dt, double dp, int nx, int np,
+                                              int ntx, int nty)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    int tx, ty;
+    if (!xcd_tile(ntx, nty, tx, ty)) return;
+    const int i = tx * 256 + threadIdx.x;
     if (i >= nx) return;
-    const int j0 = blockIdx.y * R;
+    const int j0 = ty * R;
     const Foot ft = foot_of_shift((F[i] * dt) / dp);
     const int m = reduce_offset(ft.m, np, BC);
     const T a = (T)ft.a, b = (T)ft.b, g = (T)ft.g, d = (T)ft.d;
     const int base = j0 + m - 4;
+    const T *col = fin + i;
     T w[R + 10];
 #pragma unroll
-    for (int s = 0; s < R + 10; ++s) {
-        const int q = base + s;
-        if (BC == BC_PERIODIC)
-            w[s] = fin[(size_t)wrap(q, np) * nx + i];
-        else
-            w[s] = (q >= 0 && q < np) ? fin[(size_t)q * nx + i] : T(0);
-    }
-    T D[R + 1];
-#pragma unroll
-    for (int r = 0; r <= R; ++r) D[r] = second_diff(w + r + 4);
+    for (int s = 0; s < R + 10; ++s) w[s] = sample<T, BC>(col, base + s, np, (size_t)nx);
+    T Dk = second_diff(w + 4);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
+        const T Dk1 = second_diff(w + r + 5);
         const int j = j0 + r;
-        if (j < np) fout[(size_t)j * nx + i] = spline(a, b, g, d, w[r + 4], w[r + 5], D[r], D[r + 1]);
+        if (j < np) fout[(size_t)j * nx + i] = spline(a, b, g, d, w[r + 4], w[r + 5], Dk, Dk1);
+        Dk = Dk1;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Density rho_i = dp * sum_j f_ji from the 16-row partial sums: one wavefront
-// per column, lane l sums the blocks b = l mod 64 in ascending order.
+// Density rho_i = dp * sum_j f_ji from the 16-row partial sums.  One
+// workgroup per 16 columns: thread (c, g) forms the serial sums of the block
+// classes l = g, g + 16, g + 32, g + 48 (blocks b = l mod 64, ascending b) of
+// column c, so that a wavefront load reads 16 adjacent columns of 4 block
+// rows; the 64 class sums of a column are then combined by the pairwise tree
+// in LDS.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_density(const double *__restrict__ part, double *__restrict__ rho, int nx,
                                                  int nblk, double dp)
 {
-    const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= nx) return;
-    double acc = 0.0;
-    for (int b = lane; b < nblk; b += 64) acc = acc + part[(size_t)b * nx + i];
-    acc = wave_sum(acc);
-    if (lane == 0) rho[i] = dp * acc;
+    __shared__ double S[64][17];
+    const int c = threadIdx.x & 15;
+    const int g = threadIdx.x >> 4;
+    const int i = blockIdx.x * 16 + c;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < nx) {
+        for (int b0 = 0; b0 < nblk; b0 += 64) {
+            double x[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int b = b0 + g + 16 * k;
+                x[k] = b < nblk ? part[(size_t)b * nx + i] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (b0 + g + 16 * k < nblk) acc[k] = acc[k] + x[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) S[g + 16 * k][c] = acc[k];
+    __syncthreads();
+    for (int d = 32; d >= 1; d >>= 1) {
+        for (int k = threadIdx.x; k < d * 16; k += 256) {
+            const int l = k >> 4, cc = k & 15;
+            S[l][cc] = S[l][cc] + S[l + d][cc];
+        }
+        __syncthreads();
+    }
+    if (g == 0 && i < nx) rho[i] = dp * S[0][c];
 }
 
-// Magnetization of eq. (mxmydef) by one wavefront; lane 0 returns (mx, my).
-__device__ inline void magnetization(const double *__restrict__ rho, const double *__restrict__ cs,
-                                     const double *__restrict__ sn, int n, double dx, double &mx, double &my)
+// Stage n doubles into LDS (whole workgroup).
+__device__ __forceinline__ void stage(double *dst, const double *__restrict__ src, int n)
+{
+    for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
+}
+
+// Magnetization of eq. (mxmydef) by one wavefront from LDS copies of rho, cos
+// and sin; every lane returns (mx, my).
+__device__ inline void magnetization(const double *rho, const double *cs, const double *sn, int n, double dx,
+                                     double &mx, double &my)
 {
     const int lane = threadIdx.x & 63;
     double c = 0.0, s = 0.0;
@@ -269,17 +416,31 @@ __device__ inline void record_history(double *mxmy, double *hist, int64_t *hcoun
     *hcount = c + 1;
 }
 
+constexpr int FORCE_LDS_MAX = 4096;  // nx up to which rho, cos, sin are staged in LDS
+
 // HMF force, eq. (hmfmeanforce): F_i = -sin(x_i) M_x + cos(x_i) M_y.  One
 // workgroup; wavefront 0 forms (M_x, M_y).
-__global__ __launch_bounds__(256) void k_force_hmf(const double *__restrict__ rho, const double *__restrict__ cs,
-                                                   const double *__restrict__ sn, double *__restrict__ F, int n,
-                                                   double dx, double *mxmy, double *hist, int64_t *hcount,
-                                                   int64_t hcap)
+template <bool STAGED>
+__global__ __launch_bounds__(1024) void k_force_hmf(const double *__restrict__ rho, const double *__restrict__ cs,
+                                                    const double *__restrict__ sn, double *__restrict__ F, int n,
+                                                    double dx, double *mxmy, double *hist, int64_t *hcount,
+                                                    int64_t hcap)
 {
+    __shared__ double L[STAGED ? 3 * FORCE_LDS_MAX : 1];
     __shared__ double M[2];
+    const double *r = rho, *c = cs, *s = sn;
+    if (STAGED) {
+        stage(L, rho, n);
+        stage(L + FORCE_LDS_MAX, cs, n);
+        stage(L + 2 * FORCE_LDS_MAX, sn, n);
+        __syncthreads();
+        r = L;
+        c = L + FORCE_LDS_MAX;
+        s = L + 2 * FORCE_LDS_MAX;
+    }
     if (threadIdx.x < 64) {
         double mx, my;
-        magnetization(rho, cs, sn, n, dx, mx, my);
+        magnetization(r, c, s, n, dx, mx, my);
         if (threadIdx.x == 0) {
             M[0] = mx;
             M[1] = my;
@@ -288,17 +449,32 @@ __global__ __launch_bounds__(256) void k_force_hmf(const double *__restrict__ rh
     }
     __syncthreads();
     const double mx = M[0], my = M[1];
-    for (int i = threadIdx.x; i < n; i += blockDim.x) F[i] = fma(my, cs[i], -(mx * sn[i]));
+    for (int i = threadIdx.x; i < n; i += blockDim.x) F[i] = fma(my, c[i], -(mx * s[i]));
 }
 
-// Magnetization only (ring model).  One wavefront.
-__global__ __launch_bounds__(64) void k_magnetization(const double *__restrict__ rho, const double *__restrict__ cs,
-                                                      const double *__restrict__ sn, int n, double dx, double *mxmy,
-                                                      double *hist, int64_t *hcount, int64_t hcap)
+// Magnetization only (ring model).  One workgroup, wavefront 0 reduces.
+template <bool STAGED>
+__global__ __launch_bounds__(1024) void k_magnetization(const double *__restrict__ rho,
+                                                        const double *__restrict__ cs,
+                                                        const double *__restrict__ sn, int n, double dx, double *mxmy,
+                                                        double *hist, int64_t *hcount, int64_t hcap)
 {
-    double mx, my;
-    magnetization(rho, cs, sn, n, dx, mx, my);
-    if (threadIdx.x == 0) record_history(mxmy, hist, hcount, hcap, mx, my);
+    __shared__ double L[STAGED ? 3 * FORCE_LDS_MAX : 1];
+    const double *r = rho, *c = cs, *s = sn;
+    if (STAGED) {
+        stage(L, rho, n);
+        stage(L + FORCE_LDS_MAX, cs, n);
+        stage(L + 2 * FORCE_LDS_MAX, sn, n);
+        __syncthreads();
+        r = L;
+        c = L + FORCE_LDS_MAX;
+        s = L + 2 * FORCE_LDS_MAX;
+    }
+    if (threadIdx.x < 64) {
+        double mx, my;
+        magnetization(r, c, s, n, dx, mx, my);
+        if (threadIdx.x == 0) record_history(mxmy, hist, hcount, hcap, mx, my);
+    }
 }
 
 // Ring force, eq. (meanforce) with eq. (ringpot): F_i = -dx sum_k K_{(i-k)
@@ -320,18 +496,30 @@ __global__ __launch_bounds__(256) void k_force_ring(const double *__restrict__ r
 }
 
 // Sheet force, eq. (sheetpot) with V = 2 pi G |x|: F_i = K (S - 2 P_i - rho_i),
-// K = 2 pi G dx, P_i the exclusive prefix sum of rho and S its total.  One
-// wavefront: lane l scans the contiguous chunk [l c, (l+1) c), c = ceil(n/64);
-// chunk totals by an inclusive Hillis-Steele scan d = 1, 2, ..., 32.
-__global__ __launch_bounds__(64) void k_force_sheet(const double *__restrict__ rho, double *__restrict__ F, int n,
-                                                    double K)
+// K = 2 pi G dx, P_i the exclusive prefix sum of rho and S its total.
+// Wavefront 0 scans: lane l owns the contiguous chunk [l c, (l+1) c),
+// c = ceil(n/64); chunk totals by an inclusive Hillis-Steele scan
+// d = 1, 2, ..., 32.  rho is staged in LDS when it fits.
+constexpr int SHEET_LDS_MAX = 16384;
+
+template <bool STAGED>
+__global__ __launch_bounds__(1024) void k_force_sheet(const double *__restrict__ rho, double *__restrict__ F, int n,
+                                                      double K)
 {
+    __shared__ double L[STAGED ? SHEET_LDS_MAX : 1];
+    const double *r = rho;
+    if (STAGED) {
+        stage(L, rho, n);
+        __syncthreads();
+        r = L;
+    }
+    if (threadIdx.x >= 64) return;
     const int l = threadIdx.x;
     const int c = (n + 63) / 64;
     const int lo = l * c;
     const int hi = min(lo + c, n);
     double tot = 0.0;
-    for (int i = lo; i < hi; ++i) tot = tot + rho[i];
+    for (int i = lo; i < hi; ++i) tot = tot + r[i];
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
         const double v = __shfl_up(tot, d, 64);
@@ -343,8 +531,8 @@ __global__ __launch_bounds__(64) void k_force_sheet(const double *__restrict__ r
     double acc = 0.0;
     for (int i = lo; i < hi; ++i) {
         const double Pi = excl + acc;
-        F[i] = K * (fma(-2.0, Pi, S) - rho[i]);
-        acc = acc + rho[i];
+        F[i] = K * (fma(-2.0, Pi, S) - r[i]);
+        acc = acc + r[i];
     }
 }
 
@@ -472,11 +660,13 @@ __global__ __launch_bounds__(64) void k_mom_final(const double *__restrict__ col
     }
 }
 
-// Streaming copy (bandwidth ceiling): 16-byte vectors, grid-stride.
+// Streaming copy (bandwidth ceiling): one 16-byte vector per thread, one
+// 4 KiB tile per workgroup (the fastest of the copy shapes measured on the
+// chip for buffers larger than its last-level cache).
 __global__ __launch_bounds__(256) void k_copy(const double2 *__restrict__ src, double2 *__restrict__ dst, size_t n)
 {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) dst[k] = src[k];
+    const size_t k = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < n) dst[k] = src[k];
 }
 
 }  // namespace vk
