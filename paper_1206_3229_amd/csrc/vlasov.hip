@@ -37,8 +37,10 @@ int fail(int code, const std::string &msg)
 constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
-constexpr int DRIFT_NT = 128;  // threads per drift workgroup (2 columns each)
-constexpr int KICK_R = 32;
+// drift launch shape: NT threads, runs of V columns, no trim, rows requested PF ahead
+constexpr int DRIFT_NT = 128, DRIFT_V = 2, DRIFT_PF = 4;
+// kick rows per thread (measured best on 4096^2: 16 for FP64, 32 for FP32)
+template <typename T> constexpr int kick_rows() { return sizeof(T) == 8 ? 16 : 32; }
 
 // Workspace layout (byte offsets, each 256-aligned).
 struct Layout {
@@ -173,7 +175,8 @@ template <typename T>
 int launch_drift(vlasov_ctx *c, int npass, bool partials)
 {
     const vlasov_params &P = c->P;
-    const int ntx = (int)((P.nx + 2 * DRIFT_NT - 1) / (2 * DRIFT_NT)), nty = (int)c->nblk;
+    const int tw = vk::DriftShape<DRIFT_NT, DRIFT_V, 0>::TW;  // columns per workgroup
+    const int ntx = (int)((P.nx + tw - 1) / tw), nty = (int)c->nblk;
     const dim3 grid((unsigned)vk::xcd_grid(ntx, nty));
     const T *fin = (const T *)c->fcur();
     T *fout = (T *)c->fnext();
@@ -183,7 +186,7 @@ int launch_drift(vlasov_ctx *c, int npass, bool partials)
     const int nx = (int)P.nx, np = (int)P.np;
     const int kid = npass == 2 ? VLASOV_K_DRIFT2 : VLASOV_K_DRIFT;
 #define DRIFT_LAUNCH(NP, BC, PT) \
-    launch(c, kid, vk::k_drift<T, NP, BC, PT, DRIFT_NT>, grid, dim3(DRIFT_NT), fin, fout, dm, dw, part, nx, np, ntx, nty)
+    launch(c, kid, vk::k_drift<T, NP, BC, PT, DRIFT_NT, DRIFT_V, 0, DRIFT_PF>, grid, dim3(DRIFT_NT), fin, fout, dm, dw, part, nx, np, ntx, nty)
     if (P.bc_x == VLASOV_BC_PERIODIC) {
         if (npass == 2) {
             if (partials) DRIFT_LAUNCH(2, vk::BC_PERIODIC, true); else DRIFT_LAUNCH(2, vk::BC_PERIODIC, false);
@@ -260,16 +263,17 @@ template <typename T>
 int launch_kick(vlasov_ctx *c)
 {
     const vlasov_params &P = c->P;
-    const int ntx = (int)((P.nx + 255) / 256), nty = (int)((P.np + KICK_R - 1) / KICK_R);
+    constexpr int KR = kick_rows<T>();
+    const int ntx = (int)((P.nx + 255) / 256), nty = (int)((P.np + KR - 1) / KR);
     const dim3 grid((unsigned)vk::xcd_grid(ntx, nty));
     const T *fin = (const T *)c->fcur();
     T *fout = (T *)c->fnext();
     const double *F = force_ptr(c);
     if (P.bc_p == VLASOV_BC_PERIODIC)
-        launch(c, VLASOV_K_KICK, vk::k_kick<T, vk::BC_PERIODIC, KICK_R>, grid, dim3(256), fin, fout, F, P.dt, c->dp,
+        launch(c, VLASOV_K_KICK, vk::k_kick<T, vk::BC_PERIODIC, KR>, grid, dim3(256), fin, fout, F, P.dt, c->dp,
                (int)P.nx, (int)P.np, ntx, nty);
     else
-        launch(c, VLASOV_K_KICK, vk::k_kick<T, vk::BC_ZERO, KICK_R>, grid, dim3(256), fin, fout, F, P.dt, c->dp,
+        launch(c, VLASOV_K_KICK, vk::k_kick<T, vk::BC_ZERO, KR>, grid, dim3(256), fin, fout, F, P.dt, c->dp,
                (int)P.nx, (int)P.np, ntx, nty);
     int rc = check_launch("kick");
     if (rc == VLASOV_OK) c->cur ^= 1;

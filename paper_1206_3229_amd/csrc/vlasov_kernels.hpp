@@ -152,37 +152,62 @@ template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
 
-// Interpolates the two adjacent outputs q = 2u, 2u + 1 of a row from an LDS
-// window `src` (the sample of output q's cell start is src[q + 4]): three
-// stencils shared by the pair, read as six aligned pairs src[2u .. 2u + 11].
-template <typename T>
-__device__ __forceinline__ void spline_pair(const T *src, int u, T a, T b, T g, T d, T &o0, T &o1)
+// Interpolates the V adjacent outputs q = V u .. V u + V - 1 of a row from an
+// LDS window `src` (the sample at the start of output q's cell is src[q + 4]):
+// V + 1 stencils shared by the run, read as V/2 + 5 aligned pairs
+// src[V u .. V u + V + 9].
+template <typename T, int V>
+__device__ __forceinline__ void spline_run(const T *src, int u, T a, T b, T g, T d, T (&o)[V])
 {
     using V2 = typename Vec2<T>::type;
-    const V2 *p = reinterpret_cast<const V2 *>(src) + u;
-    T x[12];
+    static_assert(V % 2 == 0, "runs of even length");
+    const V2 *p = reinterpret_cast<const V2 *>(src) + (V / 2) * u;
+    T x[V + 10];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < V / 2 + 5; ++k) {
         const V2 v = p[k];
         x[2 * k] = v.x;
         x[2 * k + 1] = v.y;
     }
-    const T D0 = second_diff(x + 4), D1 = second_diff(x + 5), D2 = second_diff(x + 6);
-    o0 = spline(a, b, g, d, x[4], x[5], D0, D1);
-    o1 = spline(a, b, g, d, x[5], x[6], D1, D2);
+    T D[V + 1];
+#pragma unroll
+    for (int k = 0; k <= V; ++k) D[k] = second_diff(x + 4 + k);
+#pragma unroll
+    for (int k = 0; k < V; ++k) o[k] = spline(a, b, g, d, x[4 + k], x[5 + k], D[k], D[k + 1]);
+}
+
+// Stores V adjacent outputs at row[i .. i + V), vectorised when aligned.
+template <typename T, int V>
+__device__ __forceinline__ void store_run(T *row, int i, int nx, const T (&o)[V])
+{
+    using V2 = typename Vec2<T>::type;
+    if (i + V <= nx && (nx & 1) == 0) {
+#pragma unroll
+        for (int k = 0; k < V; k += 2) {
+            V2 w;
+            w.x = o[k];
+            w.y = o[k + 1];
+            *reinterpret_cast<V2 *>(row + i + k) = w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+            if (i + k < nx) row[i + k] = o[k];
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Steps 1 and 4 (eqs. step1, step4): drift along x, row j shifted by the
 // constant p_j tau/dx cells.  NPASS = 2 applies the half drift twice (the
 // second half drift of one step and the first of the next), keeping the
-// intermediate row in LDS.  One workgroup of NT threads: TW = 2 NT consecutive
-// columns of a block of 16 consecutive rows, two adjacent columns per thread.
-// Rows stream through two LDS window buffers; the window of each row (TW
-// columns plus the stencil and shift halo, periodic wrap or zeros) is
-// requested PF rows ahead of its use and held in registers meanwhile.  With
-// PARTIALS, also writes the serial column sum of the 16 output rows (density
-// partial sums).
+// intermediate row in LDS.  One workgroup of NT threads: TW consecutive
+// columns of a block of 16 consecutive rows, runs of V adjacent columns per
+// thread; TW = V NT - TRIM (a trim keeps the TW + 9 intermediate values of the
+// two-pass form within one run per thread).  Rows stream through two LDS window
+// buffers; the window of each row (TW columns plus the stencil and shift halo,
+// periodic wrap or zeros) is requested PF rows ahead of its use and held in
+// registers meanwhile.  With PARTIALS, also writes the serial column sum of the
+// 16 output rows (density partial sums).
 // ---------------------------------------------------------------------------
 template <typename T, int BC, int NPASS, int TW, int NT, int NLD>
 __device__ __forceinline__ void load_window(const T *__restrict__ fin, const int32_t *__restrict__ dm, int j, int i0,
@@ -208,21 +233,30 @@ __device__ __forceinline__ void load_window(const T *__restrict__ fin, const int
     }
 }
 
-template <typename T, int NPASS, int BC, bool PARTIALS, int NT>
+template <int NT, int V, int TRIM>
+struct DriftShape {
+    static constexpr int TW = V * NT - TRIM;
+};
+
+template <typename T, int NPASS, int BC, bool PARTIALS, int NT, int V, int TRIM, int PF>
 __global__ __launch_bounds__(NT) void k_drift(const T *__restrict__ fin, T *__restrict__ fout,
                                               const int32_t *__restrict__ dm, const double4 *__restrict__ dw,
                                               double *__restrict__ part, int nx, int np, int ntx, int nty)
 {
-    using V2 = typename Vec2<T>::type;
     constexpr int R = ROWS_PER_BLOCK;
-    constexpr int PF = 4;                      // rows requested ahead
-    constexpr int TW = 2 * NT;
-    constexpr int WIN = TW + 9 * NPASS;        // window samples per row
-    constexpr int LDW = (WIN + 4) & ~1;        // even row pitch; pair reads run up to 2 past the window
-    constexpr int MIDN = TW + 9;               // first-pass outputs per row (NPASS = 2)
-    constexpr int NLD = (WIN + NT - 1) / NT;   // loads per thread per row
+    constexpr int TW = DriftShape<NT, V, TRIM>::TW;
+    constexpr int WIN = TW + 9 * NPASS;          // window samples per row
+    constexpr int MIDN = TW + 9;                 // first-pass outputs per row (NPASS = 2)
+    constexpr int NRUN1 = (MIDN + V - 1) / V;    // first-pass runs per row
+    constexpr int NLD = (WIN + NT - 1) / NT;     // loads per thread per row
+    // runs read V + 10 samples from V u: pad the buffers past the last run
+    constexpr int LDW = ((NPASS == 2 ? NRUN1 * V : TW) + 10 + 1) & ~1;
+    constexpr int MIDW = NRUN1 * V > TW + 10 ? NRUN1 * V : TW + 10;  // first-pass writes, second-pass reads
+    constexpr int LDM = (MIDW + 1) & ~1;
+    static_assert(TRIM % V == 0 && TW > 0, "tile width a positive multiple of the run");
+    static_assert(LDW >= WIN, "window buffer");
     __shared__ __attribute__((aligned(16))) T win[2][LDW];
-    __shared__ __attribute__((aligned(16))) T mid[NPASS == 2 ? MIDN + 3 : 2];
+    __shared__ __attribute__((aligned(16))) T mid[NPASS == 2 ? LDM : 2];
     int tx, ty;
     if (!xcd_tile(ntx, nty, tx, ty)) return;
     const int t = threadIdx.x;
@@ -230,19 +264,23 @@ __global__ __launch_bounds__(NT) void k_drift(const T *__restrict__ fin, T *__re
     const int j0 = ty * R;
     const int nr = min(R, np - j0);
 
-    if (t < LDW - WIN) {
-        win[0][WIN + t] = T(0);
-        win[1][WIN + t] = T(0);
+    for (int s = WIN + t; s < LDW; s += NT) {
+        win[0][s] = T(0);
+        win[1][s] = T(0);
     }
-    if (NPASS == 2 && t < 3) mid[MIDN + t] = T(0);
+    if (NPASS == 2)
+        for (int s = MIDN + t; s < LDM; s += NT) mid[s] = T(0);
 
     T v[PF][NLD];
 #pragma unroll
     for (int r = 0; r < PF; ++r)
         if (r < nr) load_window<T, BC, NPASS, TW, NT, NLD>(fin, dm, j0 + r, i0, nx, v[r]);
 
-    const int i = i0 + 2 * t;  // first of this thread's two columns
-    double acc0 = 0.0, acc1 = 0.0;
+    const int i = i0 + V * t;     // first of this thread's V columns
+    const bool own = V * t < TW;  // trailing threads own no output when TRIM > 0
+    double acc[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) acc[k] = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (r < nr) {
@@ -261,44 +299,42 @@ __global__ __launch_bounds__(NT) void k_drift(const T *__restrict__ fin, T *__re
             if (NPASS == 2) {
                 // first half drift at positions i0 + m - 4 + q, q in [0, TW + 9)
                 const int m = dm[j];
-                for (int u = t; 2 * u < MIDN; u += NT) {
-                    T o0, o1;
-                    spline_pair(src, u, a, b, g, d, o0, o1);
+                for (int u = t; u < NRUN1; u += NT) {
+                    T o[V];
+                    spline_run<T, V>(src, u, a, b, g, d, o);
                     if (BC == BC_ZERO) {
-                        const int q = i0 + m - 4 + 2 * u;
-                        if (q < 0 || q >= nx) o0 = T(0);
-                        if (q + 1 < 0 || q + 1 >= nx) o1 = T(0);
+                        const int q = i0 + m - 4 + V * u;
+#pragma unroll
+                        for (int k = 0; k < V; ++k)
+                            if (q + k < 0 || q + k >= nx) o[k] = T(0);
                     }
-                    V2 o;
-                    o.x = o0;
-                    o.y = o1;
-                    reinterpret_cast<V2 *>(mid)[u] = o;
+#pragma unroll
+                    for (int k = 0; k < V; k += 2) {
+                        typename Vec2<T>::type ww;
+                        ww.x = o[k];
+                        ww.y = o[k + 1];
+                        reinterpret_cast<typename Vec2<T>::type *>(mid + V * u)[k / 2] = ww;
+                    }
                 }
                 __syncthreads();
                 src = mid;
             }
-            T o0, o1;
-            spline_pair(src, t, a, b, g, d, o0, o1);
-            T *orow = fout + (size_t)j * nx;
-            if (i + 1 < nx && (nx & 1) == 0) {
-                V2 o;
-                o.x = o0;
-                o.y = o1;
-                *reinterpret_cast<V2 *>(orow + i) = o;
-            } else {
-                if (i < nx) orow[i] = o0;
-                if (i + 1 < nx) orow[i + 1] = o1;
-            }
-            if (PARTIALS) {
-                acc0 = acc0 + (double)o0;
-                acc1 = acc1 + (double)o1;
+            if (own) {
+                T o[V];
+                spline_run<T, V>(src, t, a, b, g, d, o);
+                store_run<T, V>(fout + (size_t)j * nx, i, nx, o);
+                if (PARTIALS) {
+#pragma unroll
+                    for (int k = 0; k < V; ++k) acc[k] = acc[k] + (double)o[k];
+                }
             }
         }
     }
-    if (PARTIALS) {
+    if (PARTIALS && own) {
         double *prow = part + (size_t)ty * nx;
-        if (i < nx) prow[i] = acc0;
-        if (i + 1 < nx) prow[i + 1] = acc1;
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+            if (i + k < nx) prow[i + k] = acc[k];
     }
 }
 
@@ -499,40 +535,50 @@ __global__ __launch_bounds__(256) void k_force_ring(const double *__restrict__ r
 // K = 2 pi G dx, P_i the exclusive prefix sum of rho and S its total.
 // Wavefront 0 scans: lane l owns the contiguous chunk [l c, (l+1) c),
 // c = ceil(n/64); chunk totals by an inclusive Hillis-Steele scan
-// d = 1, 2, ..., 32.  rho is staged in LDS when it fits.
+// d = 1, 2, ..., 32.  When staged, rho is held in LDS chunk-transposed
+// (element l c + k at k 65 + l) so that the 64 lanes walking their chunks read
+// adjacent words; F is written back in place and stored coalesced.
 constexpr int SHEET_LDS_MAX = 16384;
+constexpr int SHEET_LDS_WORDS = (SHEET_LDS_MAX / 64) * 65;
 
 template <bool STAGED>
 __global__ __launch_bounds__(1024) void k_force_sheet(const double *__restrict__ rho, double *__restrict__ F, int n,
                                                       double K)
 {
-    __shared__ double L[STAGED ? SHEET_LDS_MAX : 1];
-    const double *r = rho;
-    if (STAGED) {
-        stage(L, rho, n);
-        __syncthreads();
-        r = L;
-    }
-    if (threadIdx.x >= 64) return;
-    const int l = threadIdx.x;
+    __shared__ double L[STAGED ? SHEET_LDS_WORDS : 1];
     const int c = (n + 63) / 64;
-    const int lo = l * c;
-    const int hi = min(lo + c, n);
-    double tot = 0.0;
-    for (int i = lo; i < hi; ++i) tot = tot + r[i];
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const double v = __shfl_up(tot, d, 64);
-        if (l >= d) tot = v + tot;
+    if (STAGED) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) L[(i % c) * 65 + i / c] = rho[i];
+        __syncthreads();
     }
-    double excl = __shfl_up(tot, 1, 64);
-    if (l == 0) excl = 0.0;
-    const double S = __shfl(tot, 63, 64);
-    double acc = 0.0;
-    for (int i = lo; i < hi; ++i) {
-        const double Pi = excl + acc;
-        F[i] = K * (fma(-2.0, Pi, S) - r[i]);
-        acc = acc + r[i];
+    if (threadIdx.x < 64) {
+        const int l = threadIdx.x;
+        const int len = min(c, n - l * c);  // <= 0 past the end
+        double tot = 0.0;
+        for (int k = 0; k < len; ++k) tot = tot + (STAGED ? L[k * 65 + l] : rho[l * c + k]);
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const double v = __shfl_up(tot, d, 64);
+            if (l >= d) tot = v + tot;
+        }
+        double excl = __shfl_up(tot, 1, 64);
+        if (l == 0) excl = 0.0;
+        const double S = __shfl(tot, 63, 64);
+        double acc = 0.0;
+        for (int k = 0; k < len; ++k) {
+            const double r = STAGED ? L[k * 65 + l] : rho[l * c + k];
+            const double Pi = excl + acc;
+            const double f = K * (fma(-2.0, Pi, S) - r);
+            if (STAGED)
+                L[k * 65 + l] = f;
+            else
+                F[l * c + k] = f;
+            acc = acc + r;
+        }
+    }
+    if (STAGED) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) F[i] = L[(i % c) * 65 + i / c];
     }
 }
 
