@@ -159,6 +159,86 @@ int vlasov_destroy(vlasov_ctx *c);
 const char *vlasov_last_error(void);
 
 /* ---------------------------------------------------------------------------
+ * Batches: many contexts stepped together (one persistent launch per phase).
+ * ------------------------------------------------------------------------- */
+
+#define VLASOV_BATCH_MAX 64
+
+/* Bytes of device scratch for batched stepping in chunks of chunk_cycles
+ * cycles (grid descriptors and per-cycle work tables, two sets). */
+size_t vlasov_batch_scratch_bytes(int32_t chunk_cycles);
+
+/* Advance ctxs[k] by nsteps[k] >= 0 time steps (Sec. 3, steps 1-4), for
+ * k < n <= VLASOV_BATCH_MAX distinct contexts of one storage type created on one
+ * stream; grids may differ in size, model and dt.  Every phase (drift,
+ * density, force, kick) of all grids is one persistent launch whose
+ * workgroups stride over the tiles of all grids; chunk_cycles cycles are
+ * planned at a time and, with use_graph, captured once into a HIP graph and
+ * replayed.  Each grid's result is bit-identical to vlasov_step on it alone.
+ * scratch_dev: vlasov_batch_scratch_bytes(chunk_cycles) bytes, 256-aligned.
+ * Synchronises the stream before returning.  VLASOV_E_INVAL for mismatched
+ * contexts or a short scratch buffer. */
+int vlasov_batch_step(vlasov_ctx *const *ctxs, int32_t n, const int64_t *nsteps, void *scratch_dev,
+                      size_t scratch_bytes, int32_t chunk_cycles, int32_t use_graph);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop over parameter-scan simulations of uneven sizes with
+ * continuous batching.  Requests wait in FIFO order until a batch slot is free
+ * and their footprint fits in the caller's device arena; admitted requests join
+ * the running batch at the next chunk boundary, finished ones leave it and free
+ * their arena space.  Results equal those of vlasov_step on the request alone.
+ * ------------------------------------------------------------------------- */
+
+typedef struct vlasov_server vlasov_server;
+
+typedef struct {
+    vlasov_params p;  /* storage must equal the server's; hist_cap must be 0 */
+    int64_t nsteps;   /* >= 0 */
+    int32_t keep_f;   /* nonzero: keep the final f for vlasov_poll */
+    int32_t reserved;
+} vlasov_request;
+
+typedef struct {
+    int32_t status;   /* VLASOV_OK, or the failure code of this request */
+    int32_t reserved;
+    int64_t steps_done;
+    double t_submit, t_admit, t_done; /* seconds since the server was created */
+    vlasov_moments_t m;               /* diagnostics of the final f */
+} vlasov_result;
+
+/* Arena bytes an admitted request occupies (f pair and workspace). 0 if invalid. */
+size_t vlasov_request_footprint(const vlasov_params *p);
+
+/* Arena bytes the server reserves for its tables (at the start of the arena). */
+size_t vlasov_server_table_bytes(int32_t chunk_cycles);
+
+/* Create a server over the caller's device arena (256-aligned, kept until
+ * destroy).  storage: VLASOV_F32 or VLASOV_F64 for every request; max_slots
+ * <= VLASOV_BATCH_MAX grids run at once; chunk_cycles cycles per chunk.  A
+ * scheduler thread owns all GPU work, on hip_stream.  No HIP call is made
+ * before the first request is admitted. */
+int vlasov_server_create(void *arena_dev, size_t arena_bytes, void *hip_stream, int32_t storage, int32_t max_slots,
+                         int32_t chunk_cycles, int32_t use_graph, vlasov_server **out);
+
+/* Queue a request (thread-safe, non-blocking).  f0_host: [np][nx] FP64,
+ * copied.  VLASOV_E_INVAL for invalid parameters, VLASOV_E_NOMEM if the
+ * footprint exceeds the whole arena, VLASOV_E_STATE after destroy began. */
+int vlasov_submit(vlasov_server *s, const vlasov_request *r, const double *f0_host, uint64_t *ticket);
+
+/* VLASOV_PENDING while queued or running; VLASOV_OK once done: writes the
+ * result (and, if the request kept it and f_host is non-NULL, the final f as
+ * FP64 [np][nx]) and forgets the ticket.  VLASOV_E_NOTFOUND for an unknown
+ * ticket.  Thread-safe. */
+int vlasov_poll(vlasov_server *s, uint64_t ticket, vlasov_result *out, double *f_host);
+
+/* Counts of queued, running and finished-but-unpolled requests. */
+int vlasov_server_stats(vlasov_server *s, int64_t *queued, int64_t *running, int64_t *done);
+
+/* Drain every queued and running request, stop the scheduler, release host
+ * resources.  Unpolled results are discarded. */
+int vlasov_server_destroy(vlasov_server *s);
+
+/* ---------------------------------------------------------------------------
  * Measurement.
  * ------------------------------------------------------------------------- */
 

@@ -10,8 +10,9 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = [os.path.join(PKG, "csrc", "vlasov.hip")]
-DEPS = SRC + [os.path.join(PKG, "csrc", "vlasov_kernels.hpp"), os.path.join(ROOT, "include", "vlasov.h")]
+SRC = [os.path.join(PKG, "csrc", "vlasov.hip"), os.path.join(PKG, "csrc", "vlasov_batch.hip")]
+DEPS = SRC + [os.path.join(PKG, "csrc", n) for n in ("vlasov_kernels.hpp", "vlasov_internal.hpp")] + \
+    [os.path.join(ROOT, "include", "vlasov.h")]
 LIB = os.path.join(PKG, "libvlasov.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -28,6 +29,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-Wno-unused-command-line-argument",
+    "-Wno-unused-function",
     "-I" + os.path.join(ROOT, "include"),
 ]
 

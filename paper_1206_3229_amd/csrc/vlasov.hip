@@ -5,51 +5,23 @@
 // x drift (constant over a run) and the model tables (sin/cos of the angle
 // nodes, ring-potential derivative and value) with the host libm and uploads
 // them once; no transcendental function is evaluated on the device.
-#include <hip/hip_ext.h>
-#include <hip/hip_runtime.h>
-
-#include <math.h>
-#include <stdint.h>
 #include <string.h>
 
-#include <string>
-#include <vector>
+#include "vlasov_internal.hpp"
 
-#include "vlasov.h"
-#include "vlasov_kernels.hpp"
+using namespace vlasov_detail;
 
 namespace {
-
 thread_local std::string g_err;
+}
+
+namespace vlasov_detail {
 
 int fail(int code, const std::string &msg)
 {
     g_err = msg;
     return code;
 }
-
-#define HIP_TRY(expr)                                                                                   \
-    do {                                                                                                \
-        hipError_t e_ = (expr);                                                                         \
-        if (e_ != hipSuccess) return fail(VLASOV_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-constexpr size_t ALIGN = 256;
-size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
-
-// drift launch shape: NT threads, runs of V columns, no trim, rows requested PF ahead
-constexpr int DRIFT_NT = 128, DRIFT_V = 2, DRIFT_PF = 4;
-// kick rows per thread (measured best on 4096^2: 16 for FP64, 32 for FP32)
-template <typename T> constexpr int kick_rows() { return sizeof(T) == 8 ? 16 : 32; }
-
-// Workspace layout (byte offsets, each 256-aligned).
-struct Layout {
-    size_t drift_m, drift_w, part, rho, F, Fext, cs, sn, ringK, ringV, mxmy, hist, hcount, mom_out, mom_col,
-        mom_phi;
-    size_t total;
-};
-
-int64_t nblocks(int64_t np) { return (np + vk::ROWS_PER_BLOCK - 1) / vk::ROWS_PER_BLOCK; }
 
 Layout layout_of(const vlasov_params &p)
 {
@@ -101,37 +73,7 @@ std::string validate(const vlasov_params *p)
     return "";
 }
 
-}  // namespace
-
-struct vlasov_ctx {
-    vlasov_params P;
-    hipStream_t stream;
-    size_t s;  // bytes per stored value
-    char *f[2];
-    int cur;
-    char *ws;
-    Layout L;
-    double dx, dp;
-    int64_t nblk;
-    bool have_force;
-    // host copies kept alive for asynchronous uploads
-    std::vector<int32_t> h_dm;
-    std::vector<double4> h_dw;
-    // profiling
-    bool prof;
-    struct Rec {
-        int kid;
-        hipEvent_t a, b;
-    };
-    std::vector<Rec> recs;
-    std::vector<hipEvent_t> pool;
-    double ms[VLASOV_K_COUNT];
-    int64_t cnt[VLASOV_K_COUNT];
-
-    template <typename U> U *at(size_t off) const { return reinterpret_cast<U *>(ws + off); }
-    void *fcur() const { return f[cur]; }
-    void *fnext() const { return f[cur ^ 1]; }
-};
+}  // namespace vlasov_detail
 
 namespace {
 
@@ -210,12 +152,6 @@ int drift(vlasov_ctx *c, int npass, bool partials)
 {
     return c->P.storage == VLASOV_F32 ? launch_drift<float>(c, npass, partials)
                                       : launch_drift<double>(c, npass, partials);
-}
-
-// Force array read by the kick: the caller's table for the EXTERNAL model.
-const double *force_ptr(const vlasov_ctx *c)
-{
-    return c->at<double>(c->P.model == VLASOV_MODEL_EXTERNAL ? c->L.Fext : c->L.F);
 }
 
 // Density from the partial sums, then the model force (and magnetization).

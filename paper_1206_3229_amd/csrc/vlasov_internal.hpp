@@ -1,0 +1,89 @@
+// Internal declarations shared by the host sources of the library (not part
+// of the C ABI): the context, the workspace layout and small helpers.
+#pragma once
+
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "vlasov.h"
+#include "vlasov_kernels.hpp"
+
+namespace vlasov_detail {
+
+// Records the message of a failure for vlasov_last_error() and returns code.
+int fail(int code, const std::string &msg);
+
+#define HIP_TRY(expr)                                                                                   \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess)                                                                           \
+            return ::vlasov_detail::fail(VLASOV_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+// drift launch shape: NT threads, runs of V columns, no trim, rows requested PF ahead
+constexpr int DRIFT_NT = 128, DRIFT_V = 2, DRIFT_PF = 4;
+// kick rows per thread (measured best on 4096^2: 16 for FP64, 32 for FP32)
+template <typename T> constexpr int kick_rows() { return sizeof(T) == 8 ? 16 : 32; }
+
+// Workspace layout (byte offsets, each 256-aligned).
+struct Layout {
+    size_t drift_m, drift_w, part, rho, F, Fext, cs, sn, ringK, ringV, mxmy, hist, hcount, mom_out, mom_col,
+        mom_phi;
+    size_t total;
+};
+
+inline int64_t nblocks(int64_t np) { return (np + vk::ROWS_PER_BLOCK - 1) / vk::ROWS_PER_BLOCK; }
+
+Layout layout_of(const vlasov_params &p);
+
+// "" if the parameters are valid, else the reason.
+std::string validate(const vlasov_params *p);
+
+}  // namespace vlasov_detail
+
+struct vlasov_ctx {
+    vlasov_params P;
+    hipStream_t stream;
+    size_t s;  // bytes per stored value
+    char *f[2];
+    int cur;
+    char *ws;
+    vlasov_detail::Layout L;
+    double dx, dp;
+    int64_t nblk;
+    bool have_force;
+    // host copies kept alive for asynchronous uploads
+    std::vector<int32_t> h_dm;
+    std::vector<double4> h_dw;
+    // profiling
+    bool prof;
+    struct Rec {
+        int kid;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    double ms[VLASOV_K_COUNT];
+    int64_t cnt[VLASOV_K_COUNT];
+
+    template <typename U> U *at(size_t off) const { return reinterpret_cast<U *>(ws + off); }
+    void *fcur() const { return f[cur]; }
+    void *fnext() const { return f[cur ^ 1]; }
+};
+
+namespace vlasov_detail {
+// Force array read by the kick: the caller's table for the EXTERNAL model.
+inline const double *force_ptr(const vlasov_ctx *c)
+{
+    return c->at<double>(c->P.model == VLASOV_MODEL_EXTERNAL ? c->L.Fext : c->L.F);
+}
+}  // namespace vlasov_detail

@@ -233,40 +233,48 @@ __device__ __forceinline__ void load_window(const T *__restrict__ fin, const int
     }
 }
 
+// Geometry of a drift tile: NT threads, runs of V columns, TW = V NT - TRIM
+// columns; buffer sizes of the row window and of the first-pass row.
+template <int NPASS, int NT, int V, int TRIM>
+struct DriftGeom {
+    static constexpr int TW = V * NT - TRIM;
+    static constexpr int WIN = TW + 9 * NPASS;        // window samples per row
+    static constexpr int MIDN = TW + 9;               // first-pass outputs per row (NPASS = 2)
+    static constexpr int NRUN1 = (MIDN + V - 1) / V;  // first-pass runs per row
+    static constexpr int NLD = (WIN + NT - 1) / NT;   // loads per thread per row
+    // runs read V + 10 samples from V u: pad the buffers past the last run
+    static constexpr int LDW = ((NPASS == 2 ? NRUN1 * V : TW) + 10 + 1) & ~1;
+    static constexpr int MIDW = NRUN1 * V > TW + 10 ? NRUN1 * V : TW + 10;
+    static constexpr int LDM = NPASS == 2 ? (MIDW + 1) & ~1 : 2;
+    static_assert(TRIM % V == 0 && TW > 0, "tile width a positive multiple of the run");
+    static_assert(LDW >= WIN, "window buffer");
+};
+
 template <int NT, int V, int TRIM>
 struct DriftShape {
     static constexpr int TW = V * NT - TRIM;
 };
 
+// One drift tile (columns [tx TW, (tx+1) TW) of rows [16 ty, 16 ty + 16)).
+// win: two LDS row buffers of pitch LDW, mid: LDS row of LDM (NPASS = 2).
 template <typename T, int NPASS, int BC, bool PARTIALS, int NT, int V, int TRIM, int PF>
-__global__ __launch_bounds__(NT) void k_drift(const T *__restrict__ fin, T *__restrict__ fout,
-                                              const int32_t *__restrict__ dm, const double4 *__restrict__ dw,
-                                              double *__restrict__ part, int nx, int np, int ntx, int nty)
+__device__ __forceinline__ void drift_tile(const T *__restrict__ fin, T *__restrict__ fout,
+                                           const int32_t *__restrict__ dm, const double4 *__restrict__ dw,
+                                           double *__restrict__ part, int nx, int np, int tx, int ty, T *win0,
+                                           T *win1, T *mid)
 {
+    using G = DriftGeom<NPASS, NT, V, TRIM>;
     constexpr int R = ROWS_PER_BLOCK;
-    constexpr int TW = DriftShape<NT, V, TRIM>::TW;
-    constexpr int WIN = TW + 9 * NPASS;          // window samples per row
-    constexpr int MIDN = TW + 9;                 // first-pass outputs per row (NPASS = 2)
-    constexpr int NRUN1 = (MIDN + V - 1) / V;    // first-pass runs per row
-    constexpr int NLD = (WIN + NT - 1) / NT;     // loads per thread per row
-    // runs read V + 10 samples from V u: pad the buffers past the last run
-    constexpr int LDW = ((NPASS == 2 ? NRUN1 * V : TW) + 10 + 1) & ~1;
-    constexpr int MIDW = NRUN1 * V > TW + 10 ? NRUN1 * V : TW + 10;  // first-pass writes, second-pass reads
-    constexpr int LDM = (MIDW + 1) & ~1;
-    static_assert(TRIM % V == 0 && TW > 0, "tile width a positive multiple of the run");
-    static_assert(LDW >= WIN, "window buffer");
-    __shared__ __attribute__((aligned(16))) T win[2][LDW];
-    __shared__ __attribute__((aligned(16))) T mid[NPASS == 2 ? LDM : 2];
-    int tx, ty;
-    if (!xcd_tile(ntx, nty, tx, ty)) return;
+    constexpr int TW = G::TW, WIN = G::WIN, MIDN = G::MIDN, NRUN1 = G::NRUN1, NLD = G::NLD, LDW = G::LDW,
+                  LDM = G::LDM;
     const int t = threadIdx.x;
     const int i0 = tx * TW;
     const int j0 = ty * R;
     const int nr = min(R, np - j0);
 
     for (int s = WIN + t; s < LDW; s += NT) {
-        win[0][s] = T(0);
-        win[1][s] = T(0);
+        win0[s] = T(0);
+        win1[s] = T(0);
     }
     if (NPASS == 2)
         for (int s = MIDN + t; s < LDM; s += NT) mid[s] = T(0);
@@ -284,7 +292,7 @@ __global__ __launch_bounds__(NT) void k_drift(const T *__restrict__ fin, T *__re
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (r < nr) {
-            T *wrow = win[r & 1];
+            T *wrow = (r & 1) ? win1 : win0;
 #pragma unroll
             for (int k = 0; k < NLD; ++k) {
                 const int s = t + k * NT;
@@ -338,6 +346,19 @@ __global__ __launch_bounds__(NT) void k_drift(const T *__restrict__ fin, T *__re
     }
 }
 
+template <typename T, int NPASS, int BC, bool PARTIALS, int NT, int V, int TRIM, int PF>
+static __global__ __launch_bounds__(NT) void k_drift(const T *__restrict__ fin, T *__restrict__ fout,
+                                              const int32_t *__restrict__ dm, const double4 *__restrict__ dw,
+                                              double *__restrict__ part, int nx, int np, int ntx, int nty)
+{
+    using G = DriftGeom<NPASS, NT, V, TRIM>;
+    __shared__ __attribute__((aligned(16))) T win[2][G::LDW];
+    __shared__ __attribute__((aligned(16))) T mid[G::LDM];
+    int tx, ty;
+    if (!xcd_tile(ntx, nty, tx, ty)) return;
+    drift_tile<T, NPASS, BC, PARTIALS, NT, V, TRIM, PF>(fin, fout, dm, dw, part, nx, np, tx, ty, win[0], win[1], mid);
+}
+
 // ---------------------------------------------------------------------------
 // Step 3 (eq. step3): kick along p, column i shifted by F_i dt/dp cells.  One
 // thread per column and R consecutive output rows; the R + 9 samples of the
@@ -345,12 +366,10 @@ __global__ __launch_bounds__(NT) void k_drift(const T *__restrict__ fin, T *__re
 // wavefront read adjacent columns of the same rows).
 // ---------------------------------------------------------------------------
 template <typename T, int BC, int R>
-__global__ __launch_bounds__(256) void k_kick(const T *__restrict__ fin, T *__restrict__ fout,
-                                              const double *__restrict__ F, double dt, double dp, int nx, int np,
-                                              int ntx, int nty)
+__device__ __forceinline__ void kick_tile(const T *__restrict__ fin, T *__restrict__ fout,
+                                          const double *__restrict__ F, double dt, double dp, int nx, int np, int tx,
+                                          int ty)
 {
-    int tx, ty;
-    if (!xcd_tile(ntx, nty, tx, ty)) return;
     const int i = tx * 256 + threadIdx.x;
     if (i >= nx) return;
     const int j0 = ty * R;
@@ -372,6 +391,16 @@ __global__ __launch_bounds__(256) void k_kick(const T *__restrict__ fin, T *__re
     }
 }
 
+template <typename T, int BC, int R>
+static __global__ __launch_bounds__(256) void k_kick(const T *__restrict__ fin, T *__restrict__ fout,
+                                              const double *__restrict__ F, double dt, double dp, int nx, int np,
+                                              int ntx, int nty)
+{
+    int tx, ty;
+    if (!xcd_tile(ntx, nty, tx, ty)) return;
+    kick_tile<T, BC, R>(fin, fout, F, dt, dp, nx, np, tx, ty);
+}
+
 // ---------------------------------------------------------------------------
 // Density rho_i = dp * sum_j f_ji from the 16-row partial sums.  One
 // workgroup per 16 columns: thread (c, g) forms the serial sums of the block
@@ -380,13 +409,12 @@ __global__ __launch_bounds__(256) void k_kick(const T *__restrict__ fin, T *__re
 // rows; the 64 class sums of a column are then combined by the pairwise tree
 // in LDS.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_density(const double *__restrict__ part, double *__restrict__ rho, int nx,
-                                                 int nblk, double dp)
+__device__ __forceinline__ void density_block(const double *__restrict__ part, double *__restrict__ rho, int nx,
+                                              int nblk, double dp, int blk, double (*S)[17])
 {
-    __shared__ double S[64][17];
     const int c = threadIdx.x & 15;
     const int g = threadIdx.x >> 4;
-    const int i = blockIdx.x * 16 + c;
+    const int i = blk * 16 + c;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (i < nx) {
         for (int b0 = 0; b0 < nblk; b0 += 64) {
@@ -412,6 +440,13 @@ __global__ __launch_bounds__(256) void k_density(const double *__restrict__ part
         __syncthreads();
     }
     if (g == 0 && i < nx) rho[i] = dp * S[0][c];
+}
+
+static __global__ __launch_bounds__(256) void k_density(const double *__restrict__ part, double *__restrict__ rho, int nx,
+                                                 int nblk, double dp)
+{
+    __shared__ double S[64][17];
+    density_block(part, rho, nx, nblk, dp, blockIdx.x, S);
 }
 
 // Stage n doubles into LDS (whole workgroup).
@@ -455,15 +490,13 @@ __device__ inline void record_history(double *mxmy, double *hist, int64_t *hcoun
 constexpr int FORCE_LDS_MAX = 4096;  // nx up to which rho, cos, sin are staged in LDS
 
 // HMF force, eq. (hmfmeanforce): F_i = -sin(x_i) M_x + cos(x_i) M_y.  One
-// workgroup; wavefront 0 forms (M_x, M_y).
+// workgroup; wavefront 0 forms (M_x, M_y).  L: 3 FORCE_LDS_MAX doubles (STAGED).
 template <bool STAGED>
-__global__ __launch_bounds__(1024) void k_force_hmf(const double *__restrict__ rho, const double *__restrict__ cs,
-                                                    const double *__restrict__ sn, double *__restrict__ F, int n,
-                                                    double dx, double *mxmy, double *hist, int64_t *hcount,
-                                                    int64_t hcap)
+__device__ __forceinline__ void force_hmf_block(const double *__restrict__ rho, const double *__restrict__ cs,
+                                                const double *__restrict__ sn, double *__restrict__ F, int n,
+                                                double dx, double *mxmy, double *hist, int64_t *hcount, int64_t hcap,
+                                                double *L, double *M)
 {
-    __shared__ double L[STAGED ? 3 * FORCE_LDS_MAX : 1];
-    __shared__ double M[2];
     const double *r = rho, *c = cs, *s = sn;
     if (STAGED) {
         stage(L, rho, n);
@@ -488,14 +521,23 @@ __global__ __launch_bounds__(1024) void k_force_hmf(const double *__restrict__ r
     for (int i = threadIdx.x; i < n; i += blockDim.x) F[i] = fma(my, c[i], -(mx * s[i]));
 }
 
-// Magnetization only (ring model).  One workgroup, wavefront 0 reduces.
 template <bool STAGED>
-__global__ __launch_bounds__(1024) void k_magnetization(const double *__restrict__ rho,
-                                                        const double *__restrict__ cs,
-                                                        const double *__restrict__ sn, int n, double dx, double *mxmy,
-                                                        double *hist, int64_t *hcount, int64_t hcap)
+static __global__ __launch_bounds__(1024) void k_force_hmf(const double *__restrict__ rho, const double *__restrict__ cs,
+                                                    const double *__restrict__ sn, double *__restrict__ F, int n,
+                                                    double dx, double *mxmy, double *hist, int64_t *hcount,
+                                                    int64_t hcap)
 {
     __shared__ double L[STAGED ? 3 * FORCE_LDS_MAX : 1];
+    __shared__ double M[2];
+    force_hmf_block<STAGED>(rho, cs, sn, F, n, dx, mxmy, hist, hcount, hcap, L, M);
+}
+
+// Magnetization only (ring model).  One workgroup, wavefront 0 reduces.
+template <bool STAGED>
+__device__ __forceinline__ void magnetization_block(const double *__restrict__ rho, const double *__restrict__ cs,
+                                                    const double *__restrict__ sn, int n, double dx, double *mxmy,
+                                                    double *hist, int64_t *hcount, int64_t hcap, double *L)
+{
     const double *r = rho, *c = cs, *s = sn;
     if (STAGED) {
         stage(L, rho, n);
@@ -513,14 +555,22 @@ __global__ __launch_bounds__(1024) void k_magnetization(const double *__restrict
     }
 }
 
+template <bool STAGED>
+static __global__ __launch_bounds__(1024) void k_magnetization(const double *__restrict__ rho,
+                                                        const double *__restrict__ cs,
+                                                        const double *__restrict__ sn, int n, double dx, double *mxmy,
+                                                        double *hist, int64_t *hcount, int64_t hcap)
+{
+    __shared__ double L[STAGED ? 3 * FORCE_LDS_MAX : 1];
+    magnetization_block<STAGED>(rho, cs, sn, n, dx, mxmy, hist, hcount, hcap, L);
+}
+
 // Ring force, eq. (meanforce) with eq. (ringpot): F_i = -dx sum_k K_{(i-k)
-// mod n} rho_k with K the tabulated V'.  One wavefront per output.
-__global__ __launch_bounds__(256) void k_force_ring(const double *__restrict__ rho, const double *__restrict__ K,
-                                                    double *__restrict__ F, int n, double dx)
+// mod n} rho_k with K the tabulated V'.  One wavefront per output i.
+__device__ __forceinline__ void force_ring_output(const double *__restrict__ rho, const double *__restrict__ K,
+                                                  double *__restrict__ F, int n, double dx, int i)
 {
     const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= n) return;
     double acc = 0.0;
     for (int k = lane; k < n; k += 64) {
         int d = i - k;
@@ -529,6 +579,14 @@ __global__ __launch_bounds__(256) void k_force_ring(const double *__restrict__ r
     }
     acc = wave_sum(acc);
     if (lane == 0) F[i] = -(dx * acc);
+}
+
+static __global__ __launch_bounds__(256) void k_force_ring(const double *__restrict__ rho, const double *__restrict__ K,
+                                                    double *__restrict__ F, int n, double dx)
+{
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    force_ring_output(rho, K, F, n, dx, i);
 }
 
 // Sheet force, eq. (sheetpot) with V = 2 pi G |x|: F_i = K (S - 2 P_i - rho_i),
@@ -542,10 +600,9 @@ constexpr int SHEET_LDS_MAX = 16384;
 constexpr int SHEET_LDS_WORDS = (SHEET_LDS_MAX / 64) * 65;
 
 template <bool STAGED>
-__global__ __launch_bounds__(1024) void k_force_sheet(const double *__restrict__ rho, double *__restrict__ F, int n,
-                                                      double K)
+__device__ __forceinline__ void force_sheet_block(const double *__restrict__ rho, double *__restrict__ F, int n,
+                                                  double K, double *L)
 {
-    __shared__ double L[STAGED ? SHEET_LDS_WORDS : 1];
     const int c = (n + 63) / 64;
     if (STAGED) {
         for (int i = threadIdx.x; i < n; i += blockDim.x) L[(i % c) * 65 + i / c] = rho[i];
@@ -582,11 +639,19 @@ __global__ __launch_bounds__(1024) void k_force_sheet(const double *__restrict__
     }
 }
 
+template <bool STAGED>
+static __global__ __launch_bounds__(1024) void k_force_sheet(const double *__restrict__ rho, double *__restrict__ F, int n,
+                                                      double K)
+{
+    __shared__ double L[STAGED ? SHEET_LDS_WORDS : 1];
+    force_sheet_block<STAGED>(rho, F, n, K, L);
+}
+
 // ---------------------------------------------------------------------------
 // Diagnostics.  Pass 1: 16-row block sums of f, p f, p^2/2 f and f^2.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_mom_blocks(const T *__restrict__ f, double *__restrict__ scratch, int nx,
+static __global__ __launch_bounds__(256) void k_mom_blocks(const T *__restrict__ f, double *__restrict__ scratch, int nx,
                                                     int np, int nblk, double pmin, double dp)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -614,7 +679,7 @@ __global__ __launch_bounds__(256) void k_mom_blocks(const T *__restrict__ f, dou
 
 // Pass 2: column quantities col[q][i] = dp * sum over blocks (one wavefront
 // per column).
-__global__ __launch_bounds__(256) void k_mom_cols(const double *__restrict__ scratch, double *__restrict__ col,
+static __global__ __launch_bounds__(256) void k_mom_cols(const double *__restrict__ scratch, double *__restrict__ col,
                                                   int nx, int nblk, double dp)
 {
     const int lane = threadIdx.x & 63;
@@ -632,7 +697,7 @@ __global__ __launch_bounds__(256) void k_mom_cols(const double *__restrict__ scr
 // Pass 3 (ring and sheet): phi_i = sum_k V(x_i - x_k) rho_k with V the
 // tabulated ring potential, or |i - k| (sheet, in cells).
 template <bool RING>
-__global__ __launch_bounds__(256) void k_mom_phi(const double *__restrict__ rho, const double *__restrict__ V,
+static __global__ __launch_bounds__(256) void k_mom_phi(const double *__restrict__ rho, const double *__restrict__ V,
                                                  double *__restrict__ phi, int n)
 {
     const int lane = threadIdx.x & 63;
@@ -656,7 +721,7 @@ __global__ __launch_bounds__(256) void k_mom_phi(const double *__restrict__ rho,
 
 // Pass 4: totals (one wavefront).  out = {mass, momentum, kinetic, potential,
 // energy, mx, my, l2}.
-__global__ __launch_bounds__(64) void k_mom_final(const double *__restrict__ col, const double *__restrict__ phi,
+static __global__ __launch_bounds__(64) void k_mom_final(const double *__restrict__ col, const double *__restrict__ phi,
                                                   const double *__restrict__ cs, const double *__restrict__ sn,
                                                   double *__restrict__ out, int n, double dx, int model,
                                                   double wcoef)
@@ -706,10 +771,174 @@ __global__ __launch_bounds__(64) void k_mom_final(const double *__restrict__ col
     }
 }
 
+// ---------------------------------------------------------------------------
+// Batches: many grids (of one storage type) stepped together, one persistent
+// launch per phase.  A grid is described by a GridDesc; a cycle (drift,
+// density, force, kick) by a Cycle listing the member grids, what each does in
+// that cycle and the prefix offsets of their work items.  Workgroups stride
+// over the work items of all members; per-grid arithmetic is exactly that of
+// the single-grid kernels, whatever workgroup processes a tile.
+// ---------------------------------------------------------------------------
+constexpr int BATCH_MAX = 64;
+
+enum { DRIFT_NONE = 0, DRIFT_FIRST = 1, DRIFT_PAIR = 2, DRIFT_LAST = 3 };
+
+struct GridDesc {
+    void *f[2];
+    const int32_t *dm;
+    const double4 *dw;
+    double *part, *rho, *F;
+    const double *Fkick;  // force read by the kick (F, or the EXTERNAL table)
+    const double *cs, *sn, *K;
+    double *mxmy, *hist;
+    int64_t *hcount;
+    int64_t hcap;
+    int32_t nx, np, nblk, model, bc_x, bc_p;
+    double dx, dp, dt, sheetK;
+};
+
+struct Cycle {
+    int32_t n;                   // members in this cycle
+    int32_t slot[BATCH_MAX];     // GridDesc index of member a
+    int8_t drift[BATCH_MAX];     // DRIFT_* (FIRST and PAIR also write density partial sums)
+    int8_t kick[BATCH_MAX];      // density, force and kick in this cycle
+    int8_t cur[BATCH_MAX];       // current f buffer at the start of the cycle
+    int8_t pad[4];
+    int32_t off_drift[BATCH_MAX + 1], off_dens[BATCH_MAX + 1], off_force[BATCH_MAX + 1], off_kick[BATCH_MAX + 1];
+};
+
+// Member owning work item e: the last a with off[a] <= e (off[0] = 0 <= e < off[n]).
+__device__ __forceinline__ int find_member(const int32_t *off, int n, int e)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= e)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <typename T, int NT, int V, int PF>
+static __global__ __launch_bounds__(NT) void kb_drift(const GridDesc *__restrict__ gd, const Cycle *__restrict__ cy)
+{
+    using G1 = DriftGeom<1, NT, V, 0>;
+    using G2 = DriftGeom<2, NT, V, 0>;
+    constexpr int LDW = G1::LDW > G2::LDW ? G1::LDW : G2::LDW;
+    __shared__ __attribute__((aligned(16))) T win[2][LDW];
+    __shared__ __attribute__((aligned(16))) T mid[G2::LDM];
+    const int n = cy->n;
+    const int total = cy->off_drift[n];
+    for (int e = blockIdx.x; e < total; e += gridDim.x) {
+        const int a = find_member(cy->off_drift, n, e);
+        const GridDesc &g = gd[cy->slot[a]];
+        const int kind = cy->drift[a], cur = cy->cur[a];
+        const int li = e - cy->off_drift[a];
+        const int ntx = (g.nx + G1::TW - 1) / G1::TW;
+        const int tx = li % ntx, ty = li / ntx;
+        const T *fin = (const T *)g.f[cur];
+        T *fout = (T *)g.f[cur ^ 1];
+        __syncthreads();
+#define BD(NP, BC, PT)                                                                                               \
+    drift_tile<T, NP, BC, PT, NT, V, 0, PF>(fin, fout, g.dm, g.dw, g.part, g.nx, g.np, tx, ty, win[0], win[1], mid)
+        if (g.bc_x == BC_PERIODIC) {
+            if (kind == DRIFT_PAIR)
+                BD(2, BC_PERIODIC, true);
+            else if (kind == DRIFT_FIRST)
+                BD(1, BC_PERIODIC, true);
+            else
+                BD(1, BC_PERIODIC, false);
+        } else {
+            if (kind == DRIFT_PAIR)
+                BD(2, BC_ZERO, true);
+            else if (kind == DRIFT_FIRST)
+                BD(1, BC_ZERO, true);
+            else
+                BD(1, BC_ZERO, false);
+        }
+#undef BD
+    }
+}
+
+static __global__ __launch_bounds__(256) void kb_density(const GridDesc *__restrict__ gd, const Cycle *__restrict__ cy)
+{
+    __shared__ double S[64][17];
+    const int n = cy->n;
+    const int total = cy->off_dens[n];
+    for (int e = blockIdx.x; e < total; e += gridDim.x) {
+        const int a = find_member(cy->off_dens, n, e);
+        const GridDesc &g = gd[cy->slot[a]];
+        __syncthreads();
+        density_block(g.part, g.rho, g.nx, g.nblk, g.dp, e - cy->off_dens[a], S);
+    }
+}
+
+// Work items per member: HMF and sheet one workgroup; ring ceil(nx/16)
+// workgroups of 16 outputs plus one for the magnetization; EXTERNAL none.
+constexpr int BATCH_FORCE_LDS = SHEET_LDS_WORDS > 3 * FORCE_LDS_MAX ? SHEET_LDS_WORDS : 3 * FORCE_LDS_MAX;
+
+static __global__ __launch_bounds__(1024) void kb_force(const GridDesc *__restrict__ gd, const Cycle *__restrict__ cy)
+{
+    __shared__ double L[BATCH_FORCE_LDS];
+    __shared__ double M[2];
+    const int n = cy->n;
+    const int total = cy->off_force[n];
+    for (int e = blockIdx.x; e < total; e += gridDim.x) {
+        const int a = find_member(cy->off_force, n, e);
+        const GridDesc &g = gd[cy->slot[a]];
+        const int li = e - cy->off_force[a];
+        __syncthreads();
+        if (g.model == 0) {
+            if (g.nx <= FORCE_LDS_MAX)
+                force_hmf_block<true>(g.rho, g.cs, g.sn, g.F, g.nx, g.dx, g.mxmy, g.hist, g.hcount, g.hcap, L, M);
+            else
+                force_hmf_block<false>(g.rho, g.cs, g.sn, g.F, g.nx, g.dx, g.mxmy, g.hist, g.hcount, g.hcap, L, M);
+        } else if (g.model == 2) {
+            if (g.nx <= SHEET_LDS_MAX)
+                force_sheet_block<true>(g.rho, g.F, g.nx, g.sheetK, L);
+            else
+                force_sheet_block<false>(g.rho, g.F, g.nx, g.sheetK, L);
+        } else if (g.model == 1) {
+            const int nb = (g.nx + 15) / 16;
+            if (li < nb) {
+                const int i = li * 16 + (threadIdx.x >> 6);
+                if (i < g.nx) force_ring_output(g.rho, g.K, g.F, g.nx, g.dx, i);
+            } else if (g.nx <= FORCE_LDS_MAX) {
+                magnetization_block<true>(g.rho, g.cs, g.sn, g.nx, g.dx, g.mxmy, g.hist, g.hcount, g.hcap, L);
+            } else {
+                magnetization_block<false>(g.rho, g.cs, g.sn, g.nx, g.dx, g.mxmy, g.hist, g.hcount, g.hcap, L);
+            }
+        }
+    }
+}
+
+template <typename T, int R>
+static __global__ __launch_bounds__(256) void kb_kick(const GridDesc *__restrict__ gd, const Cycle *__restrict__ cy)
+{
+    const int n = cy->n;
+    const int total = cy->off_kick[n];
+    for (int e = blockIdx.x; e < total; e += gridDim.x) {
+        const int a = find_member(cy->off_kick, n, e);
+        const GridDesc &g = gd[cy->slot[a]];
+        const int li = e - cy->off_kick[a];
+        const int ntx = (g.nx + 255) / 256;
+        const int tx = li % ntx, ty = li / ntx;
+        const int cur = cy->cur[a];  // the drift of this cycle left f in buffer cur ^ 1
+        const T *fin = (const T *)g.f[cur ^ 1];
+        T *fout = (T *)g.f[cur];
+        if (g.bc_p == BC_PERIODIC)
+            kick_tile<T, BC_PERIODIC, R>(fin, fout, g.Fkick, g.dt, g.dp, g.nx, g.np, tx, ty);
+        else
+            kick_tile<T, BC_ZERO, R>(fin, fout, g.Fkick, g.dt, g.dp, g.nx, g.np, tx, ty);
+    }
+}
+
 // Streaming copy (bandwidth ceiling): one 16-byte vector per thread, one
 // 4 KiB tile per workgroup (the fastest of the copy shapes measured on the
 // chip for buffers larger than its last-level cache).
-__global__ __launch_bounds__(256) void k_copy(const double2 *__restrict__ src, double2 *__restrict__ dst, size_t n)
+static __global__ __launch_bounds__(256) void k_copy(const double2 *__restrict__ src, double2 *__restrict__ dst, size_t n)
 {
     const size_t k = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (k < n) dst[k] = src[k];

@@ -43,6 +43,20 @@ class Moments(C.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class Request(C.Structure):
+    _fields_ = [("p", Params), ("nsteps", C.c_int64), ("keep_f", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("reserved", C.c_int32), ("steps_done", C.c_int64),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double), ("m", Moments)]
+
+    def as_dict(self) -> dict:
+        d = {n: getattr(self, n) for n in ("status", "steps_done", "t_submit", "t_admit", "t_done")}
+        d["moments"] = self.m.as_dict()
+        return d
+
+
 _D = C.POINTER(C.c_double)
 _lib = None
 
@@ -76,6 +90,17 @@ def load() -> C.CDLL:
             "vlasov_profile_read": (C.c_int, [V, C.c_int32, _D, C.POINTER(C.c_int64)]),
             "vlasov_kernel_name": (C.c_char_p, [C.c_int32]),
             "vlasov_device_copy": (C.c_int, [V, V, C.c_size_t, V]),
+            "vlasov_batch_scratch_bytes": (C.c_size_t, [C.c_int32]),
+            "vlasov_batch_step": (C.c_int, [C.POINTER(V), C.c_int32, C.POINTER(C.c_int64), V, C.c_size_t,
+                                            C.c_int32, C.c_int32]),
+            "vlasov_request_footprint": (C.c_size_t, [P]),
+            "vlasov_server_table_bytes": (C.c_size_t, [C.c_int32]),
+            "vlasov_server_create": (C.c_int, [V, C.c_size_t, V, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                               C.POINTER(V)]),
+            "vlasov_submit": (C.c_int, [V, C.POINTER(Request), _D, C.POINTER(C.c_uint64)]),
+            "vlasov_poll": (C.c_int, [V, C.c_uint64, C.POINTER(Result), _D]),
+            "vlasov_server_stats": (C.c_int, [V, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+            "vlasov_server_destroy": (C.c_int, [V]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -205,6 +230,83 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def batch_step(solvers, nsteps, chunk_cycles: int = 16, use_graph: bool = True):
+    """Advance several solvers (one storage type, one stream) together with the
+    batched persistent kernels; solver k by nsteps[k] steps."""
+    torch = _torch()
+    lib = load()
+    n = len(solvers)
+    nb = lib.vlasov_batch_scratch_bytes(int(chunk_cycles))
+    if nb == 0:
+        raise VlasovError(E_INVAL, "bad chunk_cycles")
+    scratch = torch.empty(nb, dtype=torch.uint8, device=solvers[0].device)
+    ctxs = (C.c_void_p * n)(*[s._ctx for s in solvers])
+    steps = (C.c_int64 * n)(*[int(k) for k in nsteps])
+    check(lib.vlasov_batch_step(ctxs, n, steps, C.c_void_p(scratch.data_ptr()), nb, int(chunk_cycles),
+                                1 if use_graph else 0))
+    del scratch
+
+
+class Server:
+    """Continuous-batching request server over a torch-allocated device arena."""
+
+    def __init__(self, arena_bytes: int, storage: int = 1, max_slots: int = 32, chunk_cycles: int = 16,
+                 use_graph: bool = True, device: int | None = None):
+        torch = _torch()
+        lib = load()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.storage = storage
+        with torch.cuda.device(self.device):
+            self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+        srv = C.c_void_p()
+        check(lib.vlasov_server_create(C.c_void_p(self.arena.data_ptr()), int(arena_bytes),
+                                       C.c_void_p(self.stream.cuda_stream), int(storage), int(max_slots),
+                                       int(chunk_cycles), 1 if use_graph else 0, C.byref(srv)))
+        self._srv = srv
+        self._shapes = {}
+
+    def submit(self, params, f0: np.ndarray, nsteps: int, keep_f: bool = False) -> int:
+        f0 = np.ascontiguousarray(f0, dtype=np.float64)
+        assert f0.shape == (params.np_, params.nx)
+        req = Request(to_params(params, 0), int(nsteps), 1 if keep_f else 0, 0)
+        t = C.c_uint64()
+        check(load().vlasov_submit(self._srv, C.byref(req), _dptr(f0), C.byref(t)))
+        self._shapes[t.value] = (params.np_, params.nx, keep_f)
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending, else (result dict, f or None)."""
+        np_, nx, keep = self._shapes.get(ticket, (1, 1, False))
+        r = Result()
+        f = np.empty((np_, nx)) if keep else None
+        rc = check(load().vlasov_poll(self._srv, int(ticket), C.byref(r), _dptr(f) if f is not None else None))
+        if rc == PENDING:
+            return None
+        self._shapes.pop(ticket, None)
+        return r.as_dict(), f
+
+    def stats(self):
+        q, r, d = C.c_int64(), C.c_int64(), C.c_int64()
+        check(load().vlasov_server_stats(self._srv, C.byref(q), C.byref(r), C.byref(d)))
+        return q.value, r.value, d.value
+
+    def close(self):
+        if getattr(self, "_srv", None):
+            load().vlasov_server_destroy(self._srv)
+            self._srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def request_footprint(params) -> int:
+    return load().vlasov_request_footprint(C.byref(to_params(params, 0)))
 
 
 def device_copy(dst, src, nbytes: int, stream=None):

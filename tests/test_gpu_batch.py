@@ -1,0 +1,146 @@
+"""Batched stepping and the request server: every grid's result in a batch,
+and every request's result from the server, equals the same grid stepped
+alone (which equals the oracle, see test_gpu_parity.py), bit for bit."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+from paper_1206_3229_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def V():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1206_3229_amd import vlasov
+    vlasov.load()
+    return vlasov
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def mixed_cases(storage):
+    th0, p0 = I.waterbag_halfwidths(0.5, 0.69)
+    out = []
+    p = I.Params(I.MODEL_HMF, 128, 128, -math.pi, math.pi, -2.5, 2.5, 0.1, storage=storage)
+    out.append((p, I.waterbag(p, th0, p0, 1e-4, 1), 10, None))
+    p = I.Params(I.MODEL_RING, 96, 64, -math.pi, math.pi, -3.0, 3.0, 0.05, storage=storage, ring_eps=0.01)
+    out.append((p, I.waterbag(p, th0, p0, 1e-4, 2), 7, None))
+    p = I.Params(I.MODEL_SHEET, 200, 72, -10.0, 10.0, -4.0, 4.0, 0.05, bc_x=I.BC_ZERO, storage=storage)
+    out.append((p, I.waterbag(p, 1.0, 0.5, 1e-4, 3), 12, None))
+    p = I.Params(I.MODEL_EXTERNAL, 80, 48, 0.0, 1.0, -1.0, 1.0, 0.37, storage=storage)
+    out.append((p, np.random.default_rng(5).uniform(0, 1, (48, 80)), 5, np.sin(np.linspace(0, 6, 80)) * 3.1))
+    p = I.Params(I.MODEL_HMF, 600, 50, -math.pi, math.pi, -2.5, 2.5, 0.1, storage=storage)
+    out.append((p, I.waterbag(p, th0, p0, 1e-4, 4), 0, None))
+    p = I.Params(I.MODEL_HMF, 64, 512, -math.pi, math.pi, -2.5, 2.5, 0.05, storage=storage)
+    out.append((p, I.gaussian(p, 0.4, 1e-3), 9, None))
+    return out
+
+
+def _solo(V, p, f0, n, Fext, hist=0):
+    s = V.Solver(p, f0, hist_cap=hist)
+    if Fext is not None:
+        s.set_external_force(Fext)
+    s.step(n)
+    out = (s.read_f(), s.moments() if np.isfinite(s.read_f()).all() else None, s.mag_history())
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+@pytest.mark.parametrize("chunk,graph", [(4, True), (16, False), (3, True)])
+def test_batch_equals_each_grid_alone(V, storage, chunk, graph):
+    cases = mixed_cases(storage)
+    _log(f"batch storage={storage} chunk={chunk} graph={graph}")
+    solvers = []
+    for p, f0, n, Fext in cases:
+        s = V.Solver(p, f0, hist_cap=16)
+        if Fext is not None:
+            s.set_external_force(Fext)
+        solvers.append(s)
+    V.batch_step(solvers, [c[2] for c in cases], chunk_cycles=chunk, use_graph=graph)
+    for s, (p, f0, n, Fext) in zip(solvers, cases):
+        f_solo, m_solo, h_solo = _solo(V, p, f0, n, Fext, hist=16)
+        assert np.array_equal(s.read_f(), f_solo), (p.model, p.nx, p.np_)
+        assert np.array_equal(s.mag_history(), h_solo)
+        assert s.moments() == m_solo
+        s.close()
+
+
+def test_batch_then_single_steps_continue(V):
+    # a context stepped in a batch can go on with vlasov_step
+    p, f0, _ = I.hmf_waterbag_small()
+    a = V.Solver(p, f0)
+    V.batch_step([a], [6], chunk_cycles=4)
+    a.step(5)
+    b = V.Solver(p, f0)
+    b.step(11)
+    assert np.array_equal(a.read_f(), b.read_f())
+    a.close()
+    b.close()
+
+
+def test_batch_rejects_mixed_storage(V):
+    p64, f0, _ = I.hmf_waterbag_small()
+    p32 = I.Params(**{**p64.as_dict(), "storage": 1})
+    a, b = V.Solver(p64, f0), V.Solver(p32, f0)
+    with pytest.raises(V.VlasovError) as e:
+        V.batch_step([a, b], [1, 1])
+    assert e.value.code == V.E_INVAL
+    with pytest.raises(V.VlasovError):
+        V.batch_step([a, a], [1, 1])
+    a.close()
+    b.close()
+
+
+def _serve(V, cases, storage, arena_bytes, max_slots=8, chunk=8):
+    srv = V.Server(arena_bytes, storage=storage, max_slots=max_slots, chunk_cycles=chunk)
+    tickets = []
+    for p, f0, n, Fext in cases:
+        tickets.append(srv.submit(p, f0, n, keep_f=True))
+    results = {}
+    t_end = time.time() + 120
+    while len(results) < len(tickets) and time.time() < t_end:
+        for t in tickets:
+            if t not in results:
+                r = srv.poll(t)
+                if r is not None:
+                    results[t] = r
+        time.sleep(0.002)
+    srv.close()
+    assert len(results) == len(tickets), "server did not finish"
+    return [results[t] for t in tickets]
+
+
+@pytest.mark.parametrize("storage", [1, 0])
+def test_server_results_equal_solo_runs(V, storage):
+    cases = [c for c in mixed_cases(storage) if c[3] is None]
+    # arena for roughly two requests at a time: admission must queue
+    need = max(V.request_footprint(c[0]) for c in cases)
+    tables = V.load().vlasov_server_table_bytes(8)
+    _log(f"server storage={storage}, arena {tables + 2 * need} bytes")
+    res = _serve(V, cases, storage, tables + 2 * need + 4096)
+    for (r, f), (p, f0, n, _) in zip(res, cases):
+        assert r["status"] == 0 and r["steps_done"] == n
+        f_solo, m_solo, _ = _solo(V, p, f0, n, None)
+        assert np.array_equal(f, f_solo), (p.model, p.nx, p.np_)
+        assert r["moments"] == m_solo
+        assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+
+
+def test_server_mix_of_many_requests(V):
+    trace = I.serving_trace(24, seed=3, sides=(64, 128, 256), steps_range=(5, 40))
+    cases = [(q.params, q.initial_condition(), q.nsteps, None) for q in trace]
+    res = _serve(V, cases, 1, 64 << 20, max_slots=6, chunk=8)
+    for i in (0, 7, 23):
+        (r, f), (p, f0, n, _) = res[i], cases[i]
+        f_solo, m_solo, _ = _solo(V, p, f0, n, None)
+        assert np.array_equal(f, f_solo)
+        assert r["moments"] == m_solo
