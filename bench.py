@@ -14,6 +14,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -21,6 +22,8 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
 
 from paper_1206_3229_amd import inputs as I  # noqa: E402
 
@@ -131,6 +134,123 @@ def cpu_baseline(workload: str, seconds_target: float = 15.0):
             "sample": f"{nsteps} time steps of {workload} (single-threaded plain C oracle, after one untimed step)"}
 
 
+# ---------------------------------------------------------------------------
+# Serving: parameter-scan requests of uneven sizes with Poisson arrivals.
+# ---------------------------------------------------------------------------
+
+def _pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = min(len(xs) - 1, max(0, int(math.ceil(q / 100.0 * len(xs))) - 1))
+    return xs[k]
+
+
+def run_sequential_fp64(V, torch, trace, ics, keep):
+    """The requests one after another through vlasov_step in FP64 (bitwise equal
+    to the CPU oracle); returns per-request service times, moments, kept f."""
+    out = []
+    for q, f0 in zip(trace, ics):
+        p64 = I.Params(**{**q.params.as_dict(), "storage": I.STORAGE_F64})
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = V.Solver(p64, f0)
+        s.step(q.nsteps)
+        m = s.moments()
+        t1 = time.perf_counter()
+        f = s.read_f() if q.rid in keep else None
+        s.close()
+        out.append((t1 - t0, m, f))
+    return out
+
+
+def run_server(V, trace, ics, arrivals, keep, arena_bytes, max_slots, chunk):
+    import threading
+    srv = V.Server(arena_bytes, storage=I.STORAGE_F32, max_slots=max_slots, chunk_cycles=chunk)
+    tickets = [None] * len(trace)
+    start = time.perf_counter()
+
+    def submitter():
+        for k, (q, f0) in enumerate(zip(trace, ics)):
+            delay = arrivals[k] - (time.perf_counter() - start)
+            if delay > 0:
+                time.sleep(delay)
+            tickets[k] = srv.submit(q.params, f0, q.nsteps, keep_f=q.rid in keep)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    results = [None] * len(trace)
+    pending = len(trace)
+    while pending:
+        for k in range(len(trace)):
+            if results[k] is None and tickets[k] is not None:
+                r = srv.poll(tickets[k])
+                if r is not None:
+                    results[k] = r
+                    pending -= 1
+        time.sleep(0.0005)
+    th.join()
+    srv.close()
+    return results
+
+
+def serving(V, torch, nreq, seed=0, arena_bytes=2 << 30, max_slots=48, chunk=16):
+    trace = I.serving_trace(nreq, rate=math.inf, seed=seed, storage=I.STORAGE_F32)
+    ics = [q.initial_condition() for q in trace]
+    work = [q.params.nx * q.params.np_ * q.nsteps for q in trace]
+    keep = set(range(0, nreq, 32))
+    seq = run_sequential_fp64(V, torch, trace, ics, keep)
+    t_seq = sum(x[0] for x in seq)
+    burst = run_server(V, trace, ics, [0.0] * nreq, keep, arena_bytes, max_slots, chunk)
+    span = max(r[0]["t_done"] for r in burst) - min(r[0]["t_submit"] for r in burst)
+    rate = 0.5 * nreq / span
+    rng = np.random.default_rng(seed + 1)
+    arrivals = list(np.cumsum(rng.exponential(1.0 / rate, nreq)))
+    pois = run_server(V, trace, ics, arrivals, keep, arena_bytes, max_slots, chunk)
+    lat = [r[0]["t_done"] - r[0]["t_submit"] for r in pois]
+    span_p = max(r[0]["t_done"] for r in pois) - min(r[0]["t_submit"] for r in pois)
+    # sequential FP64 under the same arrivals: a single queue with the measured service times
+    t_free, lat_seq = 0.0, []
+    for a, (svc, _, _) in zip(arrivals, seq):
+        t0 = max(a, t_free)
+        t_free = t0 + svc
+        lat_seq.append(t_free - a)
+    # accuracy of the FP32-storage results against the FP64 results (the FP64
+    # path equals the CPU oracle bit for bit), per model
+    acc = {}
+    dF = []
+    names = {I.MODEL_HMF: "hmf", I.MODEL_RING: "ring", I.MODEL_SHEET: "sheet"}
+    for q, (r, f32), (_, m64, f64) in zip(trace, burst, seq):
+        m32 = r["moments"]
+        d = acc.setdefault(names[q.params.model], {"dE": [], "dM": [], "dmass": []})
+        d["dE"].append(abs(m32["energy"] - m64["energy"]) / max(abs(m64["energy"]), 1e-300))
+        d["dM"].append(math.hypot(m32["mx"] - m64["mx"], m32["my"] - m64["my"]))
+        d["dmass"].append(abs(m32["mass"] - m64["mass"]))
+        if f32 is not None and f64 is not None:
+            dF.append(float(np.max(np.abs(f32 - f64)) / max(np.max(np.abs(f64)), 1e-300)))
+    accuracy = {"f_rel_max_sampled": max(dF) if dF else None, "f_sampled_requests": len(dF)}
+    for k, d in acc.items():
+        accuracy[k] = {"requests": len(d["dE"]),
+                       **{f"energy_rel_p{q}": _pct(d["dE"], q) for q in (50, 90, 99)},
+                       "energy_rel_max": max(d["dE"]),
+                       **{f"magnetization_abs_p{q}": _pct(d["dM"], q) for q in (50, 99)},
+                       "mass_abs_p50": _pct(d["dmass"], 50), "mass_abs_max": max(d["dmass"])}
+    total = float(sum(work))
+    return {
+        "requests": nreq, "total_updates": total, "storage": "f32 f, f64 density/force/diagnostics",
+        "arena_bytes": arena_bytes, "max_slots": max_slots, "chunk_cycles": chunk,
+        "burst": {"makespan_s": span, "updates_per_s": total / span,
+                  "p50_s": _pct([r[0]["t_done"] - r[0]["t_submit"] for r in burst], 50),
+                  "p99_s": _pct([r[0]["t_done"] - r[0]["t_submit"] for r in burst], 99)},
+        "poisson": {"rate_per_s": rate, "makespan_s": span_p, "updates_per_s": total / span_p,
+                    "p50_s": _pct(lat, 50), "p99_s": _pct(lat, 99)},
+        "sequential_fp64": {"busy_s": t_seq, "updates_per_s": total / t_seq,
+                            "poisson_p50_s": _pct(lat_seq, 50), "poisson_p99_s": _pct(lat_seq, 99)},
+        "speedup_vs_sequential_fp64": (total / span) / (total / t_seq),
+        "accuracy_vs_fp64": accuracy,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +261,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-storage leg")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-kernel ceiling")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 leg and the copy ceiling")
+    ap.add_argument("--serve-requests", type=int, default=512, help="requests of the serving leg (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -200,6 +321,10 @@ def main():
                                                   for k, v in prof32.items()}}
     if not args.no_copy:
         out["copy_ceiling_GBps"] = copy_ceiling(torch, V)
+    if args.no_extras:
+        args.serve_requests = 0
+    if args.serve_requests > 0:
+        out["serving"] = serving(V, torch, args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

@@ -116,7 +116,8 @@ def waterbag_halfwidths(M0: float, U: float) -> tuple[float, float]:
 
 
 def _normalise(raw: np.ndarray, dx: float, dp: float) -> np.ndarray:
-    total = math.fsum(raw.ravel().tolist()) * dx * dp
+    # row sums by numpy, their total exactly rounded: deterministic for a given array
+    total = math.fsum(np.sum(raw, axis=1).tolist()) * dx * dp
     if not total > 0.0:
         raise ValueError("empty initial condition")
     return raw / total
@@ -135,9 +136,10 @@ def waterbag(p: Params, x0: float, p0: float, noise: float = 0.0, seed: int = 0)
     support = (np.abs(v)[:, None] <= p0) & (np.abs(x)[None, :] <= x0)
     raw = np.where(support, 1.0, 0.0)
     if noise != 0.0:
-        k = np.arange(p.nx * p.np_, dtype=np.uint64).reshape(p.np_, p.nx)
+        # draw k = j nx + i of the stream for the support nodes only
+        k = np.flatnonzero(support).astype(np.uint64)
         eta = 2.0 * uniform01(seed, k) - 1.0
-        raw = np.where(support, 1.0 + noise * eta, 0.0)
+        raw.ravel()[k.astype(np.int64)] = 1.0 + noise * eta
     return _normalise(raw, p.dx, p.dp)
 
 
