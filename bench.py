@@ -93,13 +93,15 @@ def copy_ceiling(torch, V, nbytes=1 << 30, reps=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def run_gpu(workload: str, steps: int, warmup: int, torch, V):
+def run_gpu(workload: str, steps: int, warmup: int, torch, V, tuning=None):
     """Warm up, then time exactly `steps` steps in one vlasov_step call with no
     instrumentation; then run the same number of steps again with per-kernel
     HIP events (each launch carries its own start/stop event) for the kernel
     breakdown."""
     p, f0, _ = WORKLOADS[workload]()
     s = V.Solver(p, f0)
+    if tuning is not None:
+        s.set_tuning(*tuning)
     s.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -262,6 +264,7 @@ def main():
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-kernel ceiling")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 leg and the copy ceiling")
     ap.add_argument("--serve-requests", type=int, default=512, help="requests of the serving leg (0: skip)")
+    ap.add_argument("--no-autotune", action="store_true", help="use the default launch shapes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -276,7 +279,16 @@ def main():
     V.load()
     torch.cuda.set_device(0)
 
-    p, secs, prof, mom, secs_events = run_gpu(args.workload, args.steps, args.warmup, torch, V)
+    def pick_shape(workload):
+        if args.no_autotune:
+            return None, None
+        from paper_1206_3229_amd import autotune
+        pw, fw, _ = WORKLOADS[workload]()
+        best = autotune.tune(pw, fw, use_cache=False)
+        return (best["drift_threads"], best["kick_rows"]), best
+
+    shape, tuned = pick_shape(args.workload)
+    p, secs, prof, mom, secs_events = run_gpu(args.workload, args.steps, args.warmup, torch, V, shape)
     npts = p.nx * p.np_
     value = npts * args.steps / secs
     s_bytes = 4 if p.storage == I.STORAGE_F32 else 8
@@ -307,6 +319,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "bytes_per_point": bpp, "avg_launch_us": avg_s * 1e6, "launches": dom_n},
         "kernels_us": {k: (v[0] / v[1] * 1e3 if v[1] else None) for k, v in prof.items()},
+        "launch_shape": {"drift_threads": shape[0], "kick_rows": shape[1],
+                         "autotune_us_per_step": {f"{t['drift_threads']}/{t['kick_rows']}": round(t["us_per_step"], 2)
+                                                  for t in tuned["table"]}} if shape else "default",
         "moments_end": {k: mom[k] for k in ("mass", "energy", "momentum")},
     }
     if args.no_extras:
@@ -314,8 +329,10 @@ def main():
     if not args.no_fp32:
         alt = {"sheet_4096x4096_f64": "sheet_4096x4096_f32"}.get(args.workload)
         if alt:
-            p32, secs32, prof32, _, _ = run_gpu(alt, args.steps, args.warmup, torch, V)
+            shape32, _ = pick_shape(alt)
+            p32, secs32, prof32, _, _ = run_gpu(alt, args.steps, args.warmup, torch, V, shape32)
             out["fp32_storage"] = {"workload": alt, "value": p32.nx * p32.np_ * args.steps / secs32,
+                                   "launch_shape": shape32,
                                    "ms_per_step": secs32 / args.steps * 1e3,
                                    "kernels_us": {k: (v[0] / v[1] * 1e3 if v[1] else None)
                                                   for k, v in prof32.items()}}

@@ -159,6 +159,25 @@ int vlasov_destroy(vlasov_ctx *c);
 const char *vlasov_last_error(void);
 
 /* ---------------------------------------------------------------------------
+ * Launch shapes.  Every shape computes the same arithmetic (results are
+ * bit-identical); they differ only in speed, which the autotuner measures.
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t drift_threads; /* threads per drift workgroup: 64, 128 or 256 (2 columns each) */
+    int32_t kick_rows;     /* rows per thread of the kick: 8, 16 or 32 */
+    int32_t reserved0, reserved1;
+} vlasov_tuning;
+
+/* The compiled launch shapes: writes min(cap, total) of them, *n = total. */
+int vlasov_tuning_candidates(vlasov_tuning *out, int32_t cap, int32_t *n);
+
+/* Select a compiled launch shape for a context (VLASOV_E_INVAL otherwise).
+ * Defaults: 128 drift threads, 16 (FP64) or 32 (FP32) kick rows. */
+int vlasov_set_tuning(vlasov_ctx *c, const vlasov_tuning *t);
+int vlasov_get_tuning(vlasov_ctx *c, vlasov_tuning *t);
+
+/* ---------------------------------------------------------------------------
  * Batches: many contexts stepped together (one persistent launch per phase).
  * ------------------------------------------------------------------------- */
 

@@ -113,11 +113,11 @@ int check_launch(const char *what)
     return VLASOV_OK;
 }
 
-template <typename T>
-int launch_drift(vlasov_ctx *c, int npass, bool partials)
+template <typename T, int NT>
+int launch_drift_nt(vlasov_ctx *c, int npass, bool partials)
 {
     const vlasov_params &P = c->P;
-    const int tw = vk::DriftShape<DRIFT_NT, DRIFT_V, 0>::TW;  // columns per workgroup
+    const int tw = vk::DriftShape<NT, DRIFT_V, 0>::TW;  // columns per workgroup
     const int ntx = (int)((P.nx + tw - 1) / tw), nty = (int)c->nblk;
     const dim3 grid((unsigned)vk::xcd_grid(ntx, nty));
     const T *fin = (const T *)c->fcur();
@@ -127,8 +127,9 @@ int launch_drift(vlasov_ctx *c, int npass, bool partials)
     double *part = c->at<double>(c->L.part);
     const int nx = (int)P.nx, np = (int)P.np;
     const int kid = npass == 2 ? VLASOV_K_DRIFT2 : VLASOV_K_DRIFT;
-#define DRIFT_LAUNCH(NP, BC, PT) \
-    launch(c, kid, vk::k_drift<T, NP, BC, PT, DRIFT_NT, DRIFT_V, 0, DRIFT_PF>, grid, dim3(DRIFT_NT), fin, fout, dm, dw, part, nx, np, ntx, nty)
+#define DRIFT_LAUNCH(NP, BC, PT)                                                                                      \
+    launch(c, kid, vk::k_drift<T, NP, BC, PT, NT, DRIFT_V, 0, DRIFT_PF>, grid, dim3(NT), fin, fout, dm, dw, part, nx, \
+           np, ntx, nty)
     if (P.bc_x == VLASOV_BC_PERIODIC) {
         if (npass == 2) {
             if (partials) DRIFT_LAUNCH(2, vk::BC_PERIODIC, true); else DRIFT_LAUNCH(2, vk::BC_PERIODIC, false);
@@ -146,6 +147,19 @@ int launch_drift(vlasov_ctx *c, int npass, bool partials)
     int rc = check_launch("drift");
     if (rc == VLASOV_OK) c->cur ^= 1;
     return rc;
+}
+
+template <typename T>
+int launch_drift(vlasov_ctx *c, int npass, bool partials)
+{
+    switch (c->tune.drift_threads) {
+    case 64:
+        return launch_drift_nt<T, 64>(c, npass, partials);
+    case 256:
+        return launch_drift_nt<T, 256>(c, npass, partials);
+    default:
+        return launch_drift_nt<T, 128>(c, npass, partials);
+    }
 }
 
 int drift(vlasov_ctx *c, int npass, bool partials)
@@ -195,11 +209,10 @@ int density_force(vlasov_ctx *c)
     return rc;
 }
 
-template <typename T>
-int launch_kick(vlasov_ctx *c)
+template <typename T, int KR>
+int launch_kick_r(vlasov_ctx *c)
 {
     const vlasov_params &P = c->P;
-    constexpr int KR = kick_rows<T>();
     const int ntx = (int)((P.nx + 255) / 256), nty = (int)((P.np + KR - 1) / KR);
     const dim3 grid((unsigned)vk::xcd_grid(ntx, nty));
     const T *fin = (const T *)c->fcur();
@@ -214,6 +227,19 @@ int launch_kick(vlasov_ctx *c)
     int rc = check_launch("kick");
     if (rc == VLASOV_OK) c->cur ^= 1;
     return rc;
+}
+
+template <typename T>
+int launch_kick(vlasov_ctx *c)
+{
+    switch (c->tune.kick_rows) {
+    case 8:
+        return launch_kick_r<T, 8>(c);
+    case 16:
+        return launch_kick_r<T, 16>(c);
+    default:
+        return launch_kick_r<T, 32>(c);
+    }
 }
 
 int kick(vlasov_ctx *c)
@@ -288,6 +314,9 @@ int vlasov_init(const vlasov_params *p, const double *f0_host, void *f_dev, void
     c->nblk = nblocks(p->np);
     c->have_force = false;
     c->prof = false;
+    c->tune.drift_threads = DRIFT_NT;
+    c->tune.kick_rows = p->storage == VLASOV_F32 ? kick_rows<float>() : kick_rows<double>();
+    c->tune.reserved0 = c->tune.reserved1 = 0;
     for (int k = 0; k < VLASOV_K_COUNT; ++k) {
         c->ms[k] = 0.0;
         c->cnt[k] = 0;
@@ -531,6 +560,37 @@ int vlasov_destroy(vlasov_ctx *c)
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
     delete c;
+    return VLASOV_OK;
+}
+
+int vlasov_tuning_candidates(vlasov_tuning *out, int32_t cap, int32_t *n)
+{
+    static const int nts[] = {64, 128, 256}, rs[] = {8, 16, 32};
+    if (!n || cap < 0 || (cap > 0 && !out)) return fail(VLASOV_E_INVAL, "bad argument");
+    int k = 0;
+    for (int a : nts)
+        for (int r : rs) {
+            if (k < cap) out[k] = vlasov_tuning{a, r, 0, 0};
+            ++k;
+        }
+    *n = k;
+    return VLASOV_OK;
+}
+
+int vlasov_set_tuning(vlasov_ctx *c, const vlasov_tuning *t)
+{
+    if (!c || !t) return fail(VLASOV_E_INVAL, "NULL argument");
+    const bool nt_ok = t->drift_threads == 64 || t->drift_threads == 128 || t->drift_threads == 256;
+    const bool r_ok = t->kick_rows == 8 || t->kick_rows == 16 || t->kick_rows == 32;
+    if (!nt_ok || !r_ok) return fail(VLASOV_E_INVAL, "launch shape not compiled in");
+    c->tune = *t;
+    return VLASOV_OK;
+}
+
+int vlasov_get_tuning(vlasov_ctx *c, vlasov_tuning *t)
+{
+    if (!c || !t) return fail(VLASOV_E_INVAL, "NULL argument");
+    *t = c->tune;
     return VLASOV_OK;
 }
 

@@ -61,6 +61,7 @@ struct vlasov_ctx {
     double dx, dp;
     int64_t nblk;
     bool have_force;
+    vlasov_tuning tune;  // launch shapes of the drift and kick
     // host copies kept alive for asynchronous uploads
     std::vector<int32_t> h_dm;
     std::vector<double4> h_dw;

@@ -43,6 +43,11 @@ class Moments(C.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class Tuning(C.Structure):
+    _fields_ = [("drift_threads", C.c_int32), ("kick_rows", C.c_int32), ("reserved0", C.c_int32),
+                ("reserved1", C.c_int32)]
+
+
 class Request(C.Structure):
     _fields_ = [("p", Params), ("nsteps", C.c_int64), ("keep_f", C.c_int32), ("reserved", C.c_int32)]
 
@@ -90,6 +95,9 @@ def load() -> C.CDLL:
             "vlasov_profile_read": (C.c_int, [V, C.c_int32, _D, C.POINTER(C.c_int64)]),
             "vlasov_kernel_name": (C.c_char_p, [C.c_int32]),
             "vlasov_device_copy": (C.c_int, [V, V, C.c_size_t, V]),
+            "vlasov_tuning_candidates": (C.c_int, [C.POINTER(Tuning), C.c_int32, C.POINTER(C.c_int32)]),
+            "vlasov_set_tuning": (C.c_int, [V, C.POINTER(Tuning)]),
+            "vlasov_get_tuning": (C.c_int, [V, C.POINTER(Tuning)]),
             "vlasov_batch_scratch_bytes": (C.c_size_t, [C.c_int32]),
             "vlasov_batch_step": (C.c_int, [C.POINTER(V), C.c_int32, C.POINTER(C.c_int64), V, C.c_size_t,
                                             C.c_int32, C.c_int32]),
@@ -207,6 +215,15 @@ class Solver:
         k = min(n.value, cap)
         return np.stack([mx[:k], my[:k]], axis=1)
 
+    # -- launch shapes ---------------------------------------------------
+    def set_tuning(self, drift_threads: int, kick_rows: int):
+        check(load().vlasov_set_tuning(self._ctx, C.byref(Tuning(int(drift_threads), int(kick_rows), 0, 0))))
+
+    def get_tuning(self) -> tuple[int, int]:
+        t = Tuning()
+        check(load().vlasov_get_tuning(self._ctx, C.byref(t)))
+        return t.drift_threads, t.kick_rows
+
     # -- measurement -----------------------------------------------------
     def profile(self, on: bool = True):
         check(load().vlasov_profile_enable(self._ctx, 1 if on else 0))
@@ -303,6 +320,14 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def tuning_candidates() -> list[tuple[int, int]]:
+    n = C.c_int32()
+    check(load().vlasov_tuning_candidates(None, 0, C.byref(n)))
+    arr = (Tuning * n.value)()
+    check(load().vlasov_tuning_candidates(arr, n.value, C.byref(n)))
+    return [(t.drift_threads, t.kick_rows) for t in arr]
 
 
 def request_footprint(params) -> int:
