@@ -211,24 +211,30 @@ __device__ __forceinline__ void store_run(T *row, int i, int nx, const T (&o)[V]
 // ---------------------------------------------------------------------------
 template <typename T, int BC, int NPASS, int TW, int NT, int NLD>
 __device__ __forceinline__ void load_window(const T *__restrict__ fin, const int32_t *__restrict__ dm, int j, int i0,
-                                            int nx, T (&v)[NLD])
+                                            int nx, T (&v)[NLD], uint32_t &inside)
 {
-    constexpr int WIN = TW + 9 * NPASS;
+    // Branch-free: every thread issues NLD loads at valid addresses (periodic
+    // positions wrapped, zero-extended ones clamped; slots past the window
+    // load a duplicate that is never used). For zero extension bit k of
+    // `inside` says whether slot k lies in the grid; the zero is applied when
+    // the value is written to LDS, not here, so that no use of a loaded value
+    // sits next to its load and the loads of the rows requested ahead stay in
+    // flight.
     const T *row = fin + (size_t)j * nx;
     int base = i0 + NPASS * dm[j] - 4 * NPASS;
     if (BC == BC_PERIODIC) base = wrap(base, nx);
+    inside = 0;
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
         const int s = threadIdx.x + k * NT;
-        if (s < WIN) {
-            int q = base + s;
-            if (BC == BC_PERIODIC) {
-                if (q >= nx) q -= nx;
-                if (q >= nx) q = wrap(q, nx);
-                v[k] = row[q];
-            } else {
-                v[k] = (q >= 0 && q < nx) ? row[q] : T(0);
-            }
+        int q = base + s;
+        if (BC == BC_PERIODIC) {
+            q = q >= nx ? q - nx : q;
+            q = q >= nx ? wrap(q, nx) : q;
+            v[k] = row[q];
+        } else {
+            v[k] = row[min(max(q, 0), nx - 1)];
+            inside |= (uint32_t)(q >= 0 && q < nx) << k;
         }
     }
 }
@@ -246,6 +252,11 @@ struct DriftGeom {
     static constexpr int LDW = ((NPASS == 2 ? NRUN1 * V : TW) + 10 + 1) & ~1;
     static constexpr int MIDW = NRUN1 * V > TW + 10 ? NRUN1 * V : TW + 10;
     static constexpr int LDM = NPASS == 2 ? (MIDW + 1) & ~1 : 2;
+    // allocation pitch of a window buffer: slot LDW takes the writes of lanes
+    // past the window, so that the LDS write (the only use of a prefetched
+    // value) is unconditional and the compiler cannot sink the load into a
+    // branch next to it
+    static constexpr int LDA = LDW + 2;
     static_assert(TRIM % V == 0 && TW > 0, "tile width a positive multiple of the run");
     static_assert(LDW >= WIN, "window buffer");
 };
@@ -256,8 +267,12 @@ struct DriftShape {
 };
 
 // One drift tile (columns [tx TW, (tx+1) TW) of rows [16 ty, 16 ty + 16)).
-// win: two LDS row buffers of pitch LDW, mid: LDS row of LDM (NPASS = 2).
-template <typename T, int NPASS, int BC, bool PARTIALS, int NT, int V, int TRIM, int PF>
+// win: two LDS row buffers of at least LDA entries each, mid: LDS row of LDM
+// (NPASS = 2).
+// FULL: the tile has all 16 rows and all TW columns inside the grid and nx is
+// even; then the row loop is straight-line code (no branch around a memory
+// access), which lets the loads requested ahead stay in flight.
+template <typename T, int NPASS, int BC, bool PARTIALS, int NT, int V, int TRIM, int PF, bool FULL>
 __device__ __forceinline__ void drift_tile(const T *__restrict__ fin, T *__restrict__ fout,
                                            const int32_t *__restrict__ dm, const double4 *__restrict__ dw,
                                            double *__restrict__ part, int nx, int np, int tx, int ty, T *win0,
@@ -270,7 +285,7 @@ __device__ __forceinline__ void drift_tile(const T *__restrict__ fin, T *__restr
     const int t = threadIdx.x;
     const int i0 = tx * TW;
     const int j0 = ty * R;
-    const int nr = min(R, np - j0);
+    const int nr = FULL ? R : min(R, np - j0);
 
     for (int s = WIN + t; s < LDW; s += NT) {
         win0[s] = T(0);
@@ -280,25 +295,30 @@ __device__ __forceinline__ void drift_tile(const T *__restrict__ fin, T *__restr
         for (int s = MIDN + t; s < LDM; s += NT) mid[s] = T(0);
 
     T v[PF][NLD];
+    uint32_t inside[PF];
+    static_assert(NLD <= 32, "one bit per loaded slot");
 #pragma unroll
     for (int r = 0; r < PF; ++r)
-        if (r < nr) load_window<T, BC, NPASS, TW, NT, NLD>(fin, dm, j0 + r, i0, nx, v[r]);
+        if (FULL || r < nr) load_window<T, BC, NPASS, TW, NT, NLD>(fin, dm, j0 + r, i0, nx, v[r], inside[r]);
 
-    const int i = i0 + V * t;     // first of this thread's V columns
-    const bool own = V * t < TW;  // trailing threads own no output when TRIM > 0
+    const int i = i0 + V * t;                // first of this thread's V columns
+    const bool own = FULL || V * t < TW;     // trailing threads own no output when TRIM > 0
     double acc[V];
 #pragma unroll
     for (int k = 0; k < V; ++k) acc[k] = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        if (r < nr) {
+        if (FULL || r < nr) {
             T *wrow = (r & 1) ? win1 : win0;
 #pragma unroll
             for (int k = 0; k < NLD; ++k) {
+                // slots k < NLD - 1 always lie in the window (t < NT)
                 const int s = t + k * NT;
-                if (s < WIN) wrow[s] = v[r % PF][k];
+                const T x = v[r % PF][k];
+                wrow[k < NLD - 1 || s < WIN ? s : LDW] = BC == BC_PERIODIC || (inside[r % PF] >> k & 1u) ? x : T(0);
             }
-            if (r + PF < nr) load_window<T, BC, NPASS, TW, NT, NLD>(fin, dm, j0 + r + PF, i0, nx, v[r % PF]);
+            if (FULL ? r + PF < R : r + PF < nr)
+                load_window<T, BC, NPASS, TW, NT, NLD>(fin, dm, j0 + r + PF, i0, nx, v[r % PF], inside[r % PF]);
             __syncthreads();
             const int j = j0 + r;
             const double4 w = dw[j];
@@ -330,7 +350,17 @@ __device__ __forceinline__ void drift_tile(const T *__restrict__ fin, T *__restr
             if (own) {
                 T o[V];
                 spline_run<T, V>(src, t, a, b, g, d, o);
-                store_run<T, V>(fout + (size_t)j * nx, i, nx, o);
+                if (FULL) {
+#pragma unroll
+                    for (int k = 0; k < V; k += 2) {
+                        typename Vec2<T>::type ww;
+                        ww.x = o[k];
+                        ww.y = o[k + 1];
+                        *reinterpret_cast<typename Vec2<T>::type *>(fout + (size_t)j * nx + i + k) = ww;
+                    }
+                } else {
+                    store_run<T, V>(fout + (size_t)j * nx, i, nx, o);
+                }
                 if (PARTIALS) {
 #pragma unroll
                     for (int k = 0; k < V; ++k) acc[k] = acc[k] + (double)o[k];
@@ -342,8 +372,25 @@ __device__ __forceinline__ void drift_tile(const T *__restrict__ fin, T *__restr
         double *prow = part + (size_t)ty * nx;
 #pragma unroll
         for (int k = 0; k < V; ++k)
-            if (i + k < nx) prow[i + k] = acc[k];
+            if (FULL || i + k < nx) prow[i + k] = acc[k];
     }
+}
+
+// Full tiles take the straight-line form, edge tiles the guarded one.
+template <typename T, int NPASS, int BC, bool PARTIALS, int NT, int V, int TRIM, int PF>
+__device__ __forceinline__ void drift_tile_any(const T *__restrict__ fin, T *__restrict__ fout,
+                                               const int32_t *__restrict__ dm, const double4 *__restrict__ dw,
+                                               double *__restrict__ part, int nx, int np, int tx, int ty, T *win0,
+                                               T *win1, T *mid)
+{
+    constexpr int TW = DriftGeom<NPASS, NT, V, TRIM>::TW;
+    const bool full = (ty + 1) * ROWS_PER_BLOCK <= np && (tx + 1) * TW <= nx && (nx & 1) == 0;
+    if (full)
+        drift_tile<T, NPASS, BC, PARTIALS, NT, V, TRIM, PF, true>(fin, fout, dm, dw, part, nx, np, tx, ty, win0, win1,
+                                                                  mid);
+    else
+        drift_tile<T, NPASS, BC, PARTIALS, NT, V, TRIM, PF, false>(fin, fout, dm, dw, part, nx, np, tx, ty, win0, win1,
+                                                                   mid);
 }
 
 template <typename T, int NPASS, int BC, bool PARTIALS, int NT, int V, int TRIM, int PF>
@@ -352,11 +399,11 @@ static __global__ __launch_bounds__(NT) void k_drift(const T *__restrict__ fin, 
                                               double *__restrict__ part, int nx, int np, int ntx, int nty)
 {
     using G = DriftGeom<NPASS, NT, V, TRIM>;
-    __shared__ __attribute__((aligned(16))) T win[2][G::LDW];
+    __shared__ __attribute__((aligned(16))) T win[2][G::LDA];
     __shared__ __attribute__((aligned(16))) T mid[G::LDM];
     int tx, ty;
     if (!xcd_tile(ntx, nty, tx, ty)) return;
-    drift_tile<T, NPASS, BC, PARTIALS, NT, V, TRIM, PF>(fin, fout, dm, dw, part, nx, np, tx, ty, win[0], win[1], mid);
+    drift_tile_any<T, NPASS, BC, PARTIALS, NT, V, TRIM, PF>(fin, fout, dm, dw, part, nx, np, tx, ty, win[0], win[1], mid);
 }
 
 // ---------------------------------------------------------------------------
@@ -826,8 +873,8 @@ static __global__ __launch_bounds__(NT) void kb_drift(const GridDesc *__restrict
 {
     using G1 = DriftGeom<1, NT, V, 0>;
     using G2 = DriftGeom<2, NT, V, 0>;
-    constexpr int LDW = G1::LDW > G2::LDW ? G1::LDW : G2::LDW;
-    __shared__ __attribute__((aligned(16))) T win[2][LDW];
+    constexpr int LDA = G1::LDA > G2::LDA ? G1::LDA : G2::LDA;
+    __shared__ __attribute__((aligned(16))) T win[2][LDA];
     __shared__ __attribute__((aligned(16))) T mid[G2::LDM];
     const int n = cy->n;
     const int total = cy->off_drift[n];
@@ -842,7 +889,7 @@ static __global__ __launch_bounds__(NT) void kb_drift(const GridDesc *__restrict
         T *fout = (T *)g.f[cur ^ 1];
         __syncthreads();
 #define BD(NP, BC, PT)                                                                                               \
-    drift_tile<T, NP, BC, PT, NT, V, 0, PF>(fin, fout, g.dm, g.dw, g.part, g.nx, g.np, tx, ty, win[0], win[1], mid)
+    drift_tile_any<T, NP, BC, PT, NT, V, 0, PF>(fin, fout, g.dm, g.dw, g.part, g.nx, g.np, tx, ty, win[0], win[1], mid)
         if (g.bc_x == BC_PERIODIC) {
             if (kind == DRIFT_PAIR)
                 BD(2, BC_PERIODIC, true);
