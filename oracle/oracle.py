@@ -15,7 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "vlasov_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
+# R8: sin and cos are called on their own (no merging into sincos)
 CFLAGS = ["-O2", "-fPIC", "-shared", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+          "-fno-builtin-sin", "-fno-builtin-cos", "-fno-builtin-sincos",
           "-Wall", "-Wextra", "-Wno-unused-parameter"]
 
 

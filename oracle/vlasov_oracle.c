@@ -29,7 +29,14 @@
  *   R5  force integrals by the rectangle rule on the grid;
  *   R6  fixed association of every sum (needed for run-to-run and
  *       implementation-independent bit patterns): see sum64 below;
- *   R7  the mean-field potentials are normalised to unit total mass.
+ *   R7  the mean-field potentials are normalised to unit total mass;
+ *   R8  sines, cosines and square roots of the node tables (eqs. mxmydef,
+ *       hmfmeanforce, ringpot) are the C library's sin, cos and sqrt of each
+ *       argument, each called on its own.  The file must therefore also be
+ *       compiled with -fno-builtin-sin -fno-builtin-cos -fno-builtin-sincos:
+ *       gcc otherwise merges a sin and a cos of one argument into a sincos
+ *       call, whose result can differ in the last bit where the exact value
+ *       lies almost half-way between two doubles.
  */
 #include <math.h>
 #include <stdint.h>

@@ -49,6 +49,27 @@ def test_hmf_force_is_the_sine_convolution(oracle, nx):
     assert abs(my - p.dx * math.fsum((np.sin(x) * rho).tolist())) < 1e-15 * 8
 
 
+def test_node_sines_are_the_correctly_rounded_library_values(oracle):
+    # On the 1100-node angle grid, sin(x_241) lies within 0.0003 ulp of the
+    # half-way point between two doubles; the C library's sin rounds it
+    # correctly, its sincos does not.  A density concentrated on one node
+    # gives M = dx (sin x_k, cos x_k) * 1, so the oracle's magnetization must
+    # carry exactly the library's sin and cos of that node (the transcendental
+    # values of eq. (mxmydef) are the C library's sin and cos, called on
+    # their own).
+    p = _params(I.MODEL_HMF, 1100)
+    x = I.nodes(1100, p.xmin, p.xmax)
+    for k in (241, 859, 3, 550):
+        rho = np.zeros(1100)
+        rho[k] = 1.0
+        _, (mx, my) = oracle.force(p, rho)
+        assert my == p.dx * math.sin(x[k]) and mx == p.dx * math.cos(x[k]), k
+    # the oracle library binds sin and cos themselves, never sincos
+    import subprocess
+    syms = subprocess.run(["nm", "-D", oracle.LIB], capture_output=True, text=True).stdout
+    assert " sin@" in syms.replace("U sin@", " sin@") and "sincos" not in syms
+
+
 @pytest.mark.parametrize("nx", [16, 64, 129])
 def test_ring_force_derivative_of_potential(oracle, nx):
     # eq. (ringpot) with eps = 0.5: F(x_i) = -d/dx [dx sum_k V(x - x_k) rho_k] at x_i,
