@@ -50,20 +50,26 @@ def kernel_source_hash() -> str:
 
 def algorithmic_bytes_per_point(kernel: str, s: int) -> float:
     """Bytes per grid point one launch must move: read f and write f once
-    (s bytes each); the drifts also write one FP64 partial sum per 16 rows."""
-    if kernel in ("drift", "drift2"):
+    (s bytes each); the drifts that feed the next force also write one FP64
+    partial sum per 16 rows.  The fused kick and drift moves the same bytes
+    as one drift: f once in, once out."""
+    if kernel in ("drift", "drift2", "kick_drift2"):
         return 2 * s + 8.0 / 16.0
-    if kernel == "kick":
+    if kernel in ("kick", "kick_drift"):
         return 2.0 * s
     if kernel == "moments":
         return s + 4 * 8.0 / 16.0
     return float("nan")
 
 
-def measured_traffic(workload: str, kernel: str):
+def shape_str(shape) -> str:
+    return "/".join(str(int(v)) for v in shape)
+
+
+def measured_traffic(workload: str, kernel: str, shape):
     """HBM bytes per launch from the committed rocprofv3 counter summary
     (profiles/pmc_<workload>.txt), if it was taken on the current kernel
-    sources; else None."""
+    sources in the same launch shape; else None."""
     path = os.path.join(ROOT, "profiles", f"pmc_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -71,7 +77,8 @@ def measured_traffic(workload: str, kernel: str):
     m = re.search(r"^kernel_source_hash: (\S+)$", text, re.M)
     if not m or m.group(1) != kernel_source_hash():
         return None
-    m = re.search(rf"^kernel {re.escape(kernel)}: hbm_bytes_per_launch=(\S+)$", text, re.M)
+    m = re.search(rf"^kernel {re.escape(kernel)} shape {re.escape(shape_str(shape))}: hbm_bytes_per_launch=(\S+)$",
+                  text, re.M)
     return float(m.group(1)) if m else None
 
 
@@ -265,6 +272,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 leg and the copy ceiling")
     ap.add_argument("--serve-requests", type=int, default=512, help="requests of the serving leg (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch shapes")
+    ap.add_argument("--shape", default=None,
+                    help="fixed launch shape drift_threads/kick_rows/kick_drift_width (no autotuning)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -280,12 +289,14 @@ def main():
     torch.cuda.set_device(0)
 
     def pick_shape(workload):
+        if args.shape:
+            return tuple(int(v) for v in args.shape.split("/")), None
         if args.no_autotune:
             return None, None
         from paper_1206_3229_amd import autotune
         pw, fw, _ = WORKLOADS[workload]()
         best = autotune.tune(pw, fw, use_cache=False)
-        return (best["drift_threads"], best["kick_rows"]), best
+        return (best["drift_threads"], best["kick_rows"], best["kick_drift_width"]), best
 
     shape, tuned = pick_shape(args.workload)
     p, secs, prof, mom, secs_events = run_gpu(args.workload, args.steps, args.warmup, torch, V, shape)
@@ -298,7 +309,7 @@ def main():
     avg_s = dom_ms / dom_n * 1e-3
     bpp = algorithmic_bytes_per_point(dom, s_bytes)
     achieved = bpp * npts / avg_s / 1e9
-    traffic = measured_traffic(args.workload, dom)
+    traffic = measured_traffic(args.workload, dom, shape) if shape else None
     out = {
         "metric": "grid-point updates/s per Strang step",
         "value": value,
@@ -319,9 +330,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "bytes_per_point": bpp, "avg_launch_us": avg_s * 1e6, "launches": dom_n},
         "kernels_us": {k: (v[0] / v[1] * 1e3 if v[1] else None) for k, v in prof.items()},
-        "launch_shape": {"drift_threads": shape[0], "kick_rows": shape[1],
-                         "autotune_us_per_step": {f"{t['drift_threads']}/{t['kick_rows']}": round(t["us_per_step"], 2)
-                                                  for t in tuned["table"]}} if shape else "default",
+        "launch_shape": {"drift_threads": shape[0], "kick_rows": shape[1], "kick_drift_width": shape[2],
+                         "autotune_us_per_step": {
+                             f"{t['drift_threads']}/{t['kick_rows']}/{t['kick_drift_width']}": round(t["us_per_step"], 2)
+                             for t in tuned["table"]} if tuned else "fixed"} if shape else "default",
         "moments_end": {k: mom[k] for k in ("mass", "energy", "momentum")},
     }
     if args.no_extras:

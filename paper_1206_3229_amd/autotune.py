@@ -1,7 +1,8 @@
 """Launch-shape autotuner.
 
-Times every compiled launch shape of the drift and kick kernels (threads per
-drift workgroup, rows per kick thread) on the device for one grid, keeps the
+Times every compiled launch shape (threads per drift workgroup, rows per kick
+thread, separate or fused kick and drift and the fused tile width) on the
+device for one grid, keeps the
 fastest and caches it in a JSON file keyed by the GPU architecture, the
 storage type, the grid size and the boundaries.  All shapes compute the same
 arithmetic, so the choice changes speed only, never results.
@@ -23,7 +24,7 @@ def cache_path() -> str:
 
 
 def _key(arch: str, p) -> str:
-    return f"{arch}|s{p.storage}|{p.nx}x{p.np_}|bc{p.bc_x}{p.bc_p}"
+    return f"{arch}|s{p.storage}|{p.nx}x{p.np_}|bc{p.bc_x}{p.bc_p}|dt{p.dt!r}|v2"
 
 
 def _load_cache() -> dict:
@@ -49,7 +50,8 @@ def _store(key: str, entry: dict):
 
 
 def tune(params, f0: np.ndarray, steps: int = 10, reps: int = 3, use_cache: bool = True) -> dict:
-    """Best launch shape for this grid: {"drift_threads", "kick_rows", "us_per_step", "table"}."""
+    """Best launch shape for this grid:
+    {"drift_threads", "kick_rows", "kick_drift_width", "us_per_step", "table"}."""
     import torch
     arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName
     key = _key(arch, params)
@@ -59,8 +61,8 @@ def tune(params, f0: np.ndarray, steps: int = 10, reps: int = 3, use_cache: bool
             return hit
     s = V.Solver(params, f0)
     table = []
-    for nt, kr in V.tuning_candidates():
-        s.set_tuning(nt, kr)
+    for nt, kr, kw in V.tuning_candidates():
+        s.set_tuning(nt, kr, kw)
         s.step(2)
         times = []
         for _ in range(reps):
@@ -70,10 +72,12 @@ def tune(params, f0: np.ndarray, steps: int = 10, reps: int = 3, use_cache: bool
             e1.record()
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1) * 1e3 / steps)
-        table.append((float(np.median(times)), nt, kr))
+        table.append((float(np.median(times)), nt, kr, kw))
     s.close()
     table.sort()
-    best = {"drift_threads": table[0][1], "kick_rows": table[0][2], "us_per_step": table[0][0],
-            "table": [{"drift_threads": nt, "kick_rows": kr, "us_per_step": t} for t, nt, kr in table]}
+    best = {"drift_threads": table[0][1], "kick_rows": table[0][2], "kick_drift_width": table[0][3],
+            "us_per_step": table[0][0],
+            "table": [{"drift_threads": nt, "kick_rows": kr, "kick_drift_width": kw, "us_per_step": t}
+                      for t, nt, kr, kw in table]}
     _store(key, best)
     return best

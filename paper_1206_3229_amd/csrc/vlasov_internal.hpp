@@ -33,11 +33,13 @@ inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 constexpr int DRIFT_NT = 128, DRIFT_V = 2, DRIFT_PF = 4;
 // kick rows per thread (measured best on 4096^2: 16 for FP64, 32 for FP32)
 template <typename T> constexpr int kick_rows() { return sizeof(T) == 8 ? 16 : 32; }
+// fused kick and drift: default tile width, rows requested ahead by the kick
+constexpr int KD_TW = 512, KD_PF = 4;
 
 // Workspace layout (byte offsets, each 256-aligned).
 struct Layout {
-    size_t drift_m, drift_w, part, rho, F, Fext, cs, sn, ringK, ringV, mxmy, hist, hcount, mom_out, mom_col,
-        mom_phi;
+    size_t drift_m, drift_w, kd_base, kd_rel, part, rho, F, Fext, cs, sn, ringK, ringV, mxmy, hist, hcount, mom_out,
+        mom_col, mom_phi;
     size_t total;
 };
 
@@ -65,6 +67,10 @@ struct vlasov_ctx {
     // host copies kept alive for asynchronous uploads
     std::vector<int32_t> h_dm;
     std::vector<double4> h_dw;
+    std::vector<int32_t> h_kd_base, h_kd_rel;
+    // kick and drift can run fused for NPASS = 1 / 2 (drift shifts of every
+    // 16-row block within the kicked halo)
+    bool kd_ok[2];
     // profiling
     bool prof;
     struct Rec {

@@ -449,6 +449,220 @@ static __global__ __launch_bounds__(256) void k_kick(const T *__restrict__ fin, 
 }
 
 // ---------------------------------------------------------------------------
+// Step 3 fused with the drift that follows it (step 4, and with NPASS = 2 also
+// step 1 of the next step).  Once the force is known nothing global separates
+// the kick of a row from its drift, so one workgroup kicks the columns its
+// drift windows need and drifts the kicked rows straight from LDS: f is read
+// and written once for both sweeps.  The arithmetic of every value is that of
+// the separate kick and drift, so results are identical bit for bit.
+//
+// Tile: the 16 rows of one density block by TW output columns, NT threads.
+// The drift window of row j starts at column i0 + NPASS m_j - 4 NPASS; over
+// the block these windows lie in the KW = WIN + SPR kicked columns starting at
+// i0 + kbase (kbase = NPASS min_j m_j - 4 NPASS, reduced mod nx on a periodic
+// x axis), row j's window at offset NPASS krel_j, krel_j = m_j - min m.  A
+// grid whose blocks need NPASS krel > SPR takes the separate kernels.
+// Thread t kicks the columns kappa = t + k NT (k < KC) of that range, each
+// from a sliding window of the R + 10 samples of its column, requested PF
+// rows ahead, and writes the kicked row into the LDS window of the drift at
+// kappa - NPASS krel_j.
+// ---------------------------------------------------------------------------
+constexpr int KD_SPR = 8;
+
+template <int NPASS, int NT, int TW>
+struct KickDriftGeom {
+    static constexpr int V = 2;
+    using G = DriftGeom<NPASS, NT, V, V * NT - TW>;
+    static constexpr int KW = G::WIN + KD_SPR;      // kicked columns per row
+    static constexpr int KC = (KW + NT - 1) / NT;  // kicked columns per thread
+    static_assert(NPASS == 1 || G::NRUN1 <= NT, "one first-pass run per thread");
+    static_assert(TW <= V * NT, "one output run per thread");
+};
+
+template <typename T, int NPASS, int BCX, int BCP, bool PARTIALS, int NT, int TW, int PF, bool FULL>
+__device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__restrict__ fout,
+                                                const double *__restrict__ F, double dt, double dp,
+                                                const int32_t *__restrict__ dm, const double4 *__restrict__ dw,
+                                                const int32_t *__restrict__ kbase, const int32_t *__restrict__ krel,
+                                                double *__restrict__ part, int nx, int np, int tx, int ty, T *win0,
+                                                T *win1, T *mid)
+{
+    using KG = KickDriftGeom<NPASS, NT, TW>;
+    using G = typename KG::G;
+    constexpr int V = KG::V, KC = KG::KC, R = ROWS_PER_BLOCK, NS = R + 10;
+    constexpr int WIN = G::WIN, MIDN = G::MIDN, NRUN1 = G::NRUN1, LDW = G::LDW, LDM = G::LDM;
+    static_assert(NS <= 32, "one mask bit per sample");
+    const int t = threadIdx.x;
+    const int i0 = tx * TW;
+    const int j0 = ty * R;
+    const int nr = FULL ? R : min(R, np - j0);
+
+    for (int s = WIN + t; s < LDW; s += NT) {
+        win0[s] = T(0);
+        win1[s] = T(0);
+    }
+    if (NPASS == 2)
+        for (int s = MIDN + t; s < LDM; s += NT) mid[s] = T(0);
+
+    // Kicked columns of this thread: foot of the p shift (eq. step3), first
+    // sample row, and masks of the samples that lie inside the grid.
+    const int cL = i0 + kbase[ty];
+    const T *colp[KC];
+    int rbase[KC];
+    uint32_t inside[KC];
+    bool colin[KC];
+    T ka[KC], kb[KC], kg[KC], kd[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const int c = cL + t + k * NT;
+        int gc;
+        if (BCX == BC_PERIODIC) {
+            gc = c >= nx ? c - nx : c;
+            gc = gc >= nx ? wrap(gc, nx) : gc;
+            colin[k] = true;
+        } else {
+            gc = min(max(c, 0), nx - 1);
+            colin[k] = c >= 0 && c < nx;
+        }
+        const Foot ft = foot_of_shift((F[gc] * dt) / dp);
+        const int m = reduce_offset(ft.m, np, BCP);
+        ka[k] = (T)ft.a;
+        kb[k] = (T)ft.b;
+        kg[k] = (T)ft.g;
+        kd[k] = (T)ft.d;
+        colp[k] = fin + gc;
+        int b = j0 + m - 4;
+        if (BCP == BC_PERIODIC) b = b >= np ? b - np : (b < 0 ? b + np : b);
+        rbase[k] = b;
+        inside[k] = 0;
+    }
+    // Sample s of column k: row rbase + s, wrapped or clamped (zero rows are
+    // masked when the sample is first used, never next to its load).
+    T w[KC][NS];
+    auto request = [&](int s) {
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            int q = rbase[k] + s;
+            if (BCP == BC_PERIODIC) {
+                q = q >= np ? q - np : q;
+                q = q >= np ? q - np : q;
+            } else {
+                inside[k] |= (uint32_t)(q >= 0 && q < np) << s;
+                q = min(max(q, 0), np - 1);
+            }
+            w[k][s] = colp[k][(size_t)q * nx];
+        }
+    };
+    auto settle = [&](int s) {
+        if (BCP != BC_PERIODIC) {
+#pragma unroll
+            for (int k = 0; k < KC; ++k) w[k][s] = (inside[k] >> s & 1u) ? w[k][s] : T(0);
+        }
+    };
+#pragma unroll
+    for (int s = 0; s < 10 + PF; ++s) request(s);
+#pragma unroll
+    for (int s = 0; s < 9; ++s) settle(s);
+    T Dk[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) Dk[k] = second_diff(w[k] + 4);
+
+    const int i = i0 + V * t;
+    const bool own = FULL ? V * t < TW : (V * t < TW && i < nx);
+    double acc[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) acc[k] = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (FULL || r < nr) {
+            const int j = j0 + r;
+            T *wrow = (r & 1) ? win1 : win0;
+            settle(r + 9);
+            const int rel = NPASS * krel[j];
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                const T Dk1 = second_diff(w[k] + r + 5);
+                T y = spline(ka[k], kb[k], kg[k], kd[k], w[k][r + 4], w[k][r + 5], Dk[k], Dk1);
+                Dk[k] = Dk1;
+                if (BCX != BC_PERIODIC) y = colin[k] ? y : T(0);
+                const int pos = t + k * NT - rel;
+                wrow[(unsigned)pos < (unsigned)WIN ? pos : LDW] = y;
+            }
+            if (r + 10 + PF < NS) request(r + 10 + PF);
+            __syncthreads();
+            const double4 wd = dw[j];
+            const T a = (T)wd.x, b = (T)wd.y, g = (T)wd.z, d = (T)wd.w;
+            const T *src = wrow;
+            if (NPASS == 2) {
+                // first half drift at positions i0 + m - 4 + q, q in [0, TW + 9)
+                const int m = dm[j];
+                if (t < NRUN1) {
+                    T o[V];
+                    spline_run<T, V>(src, t, a, b, g, d, o);
+                    if (BCX == BC_ZERO) {
+                        const int q = i0 + m - 4 + V * t;
+#pragma unroll
+                        for (int k = 0; k < V; ++k)
+                            if (q + k < 0 || q + k >= nx) o[k] = T(0);
+                    }
+                    typename Vec2<T>::type ww;
+                    ww.x = o[0];
+                    ww.y = o[1];
+                    reinterpret_cast<typename Vec2<T>::type *>(mid)[t] = ww;
+                }
+                __syncthreads();
+                src = mid;
+            }
+            if (own) {
+                T o[V];
+                spline_run<T, V>(src, t, a, b, g, d, o);
+                if (FULL) {
+                    typename Vec2<T>::type ww;
+                    ww.x = o[0];
+                    ww.y = o[1];
+                    *reinterpret_cast<typename Vec2<T>::type *>(fout + (size_t)j * nx + i) = ww;
+                } else {
+                    store_run<T, V>(fout + (size_t)j * nx, i, nx, o);
+                }
+                if (PARTIALS) {
+#pragma unroll
+                    for (int k = 0; k < V; ++k) acc[k] = acc[k] + (double)o[k];
+                }
+            }
+        }
+    }
+    if (PARTIALS && own) {
+        double *prow = part + (size_t)ty * nx;
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+            if (FULL || i + k < nx) prow[i + k] = acc[k];
+    }
+}
+
+template <typename T, int NPASS, int BCX, int BCP, bool PARTIALS, int NT, int TW, int PF>
+static __global__ __launch_bounds__(NT) void k_kick_drift(const T *__restrict__ fin, T *__restrict__ fout,
+                                                   const double *__restrict__ F, double dt, double dp,
+                                                   const int32_t *__restrict__ dm,
+                                                   const double4 *__restrict__ dw,
+                                                   const int32_t *__restrict__ kbase,
+                                                   const int32_t *__restrict__ krel, double *__restrict__ part,
+                                                   int nx, int np, int ntx, int nty)
+{
+    using G = typename KickDriftGeom<NPASS, NT, TW>::G;
+    __shared__ __attribute__((aligned(16))) T win[2][G::LDA];
+    __shared__ __attribute__((aligned(16))) T mid[G::LDM];
+    int tx, ty;
+    if (!xcd_tile(ntx, nty, tx, ty)) return;
+    const bool full = (ty + 1) * ROWS_PER_BLOCK <= np && (tx + 1) * TW <= nx && (nx & 1) == 0;
+    if (full)
+        kick_drift_tile<T, NPASS, BCX, BCP, PARTIALS, NT, TW, PF, true>(fin, fout, F, dt, dp, dm, dw, kbase, krel,
+                                                                        part, nx, np, tx, ty, win[0], win[1], mid);
+    else
+        kick_drift_tile<T, NPASS, BCX, BCP, PARTIALS, NT, TW, PF, false>(fin, fout, F, dt, dp, dm, dw, kbase, krel,
+                                                                         part, nx, np, tx, ty, win[0], win[1], mid);
+}
+
+// ---------------------------------------------------------------------------
 // Density rho_i = dp * sum_j f_ji from the 16-row partial sums.  One
 // workgroup per 16 columns: thread (c, g) forms the serial sums of the block
 // classes l = g, g + 16, g + 32, g + 48 (blocks b = l mod 64, ascending b) of

@@ -150,19 +150,22 @@ def test_every_launch_shape_gives_identical_results(V):
     p = I.Params(I.MODEL_SHEET, 600, 90, -10.0, 10.0, -4.0, 4.0, 0.05, bc_x=I.BC_ZERO)
     f0 = I.waterbag(p, 1.0, 0.5, 1e-4, 3)
     ref = None
-    for nt, kr in V.tuning_candidates():
+    for shape in V.tuning_candidates():
         s = V.Solver(p, f0)
-        s.set_tuning(nt, kr)
-        assert s.get_tuning() == (nt, kr)
+        s.set_tuning(*shape)
+        assert s.get_tuning() == shape
         s.step(7)
         f = s.read_f()
         s.close()
         if ref is None:
             ref = f
-        assert np.array_equal(f, ref), (nt, kr)
+        assert np.array_equal(f, ref), shape
+    assert {w for _, _, w in V.tuning_candidates()} == {0, 256, 512}
     s = V.Solver(p, f0)
     with pytest.raises(V.VlasovError):
         s.set_tuning(96, 16)
+    with pytest.raises(V.VlasovError):
+        s.set_tuning(128, 16, 384)
     s.close()
 
 
@@ -171,6 +174,6 @@ def test_autotune_picks_a_compiled_shape(V, tmp_path, monkeypatch):
     monkeypatch.setenv("VLASOV_TUNE_CACHE", str(tmp_path / "tune.json"))
     p, f0, _ = I.hmf_waterbag_small()
     best = autotune.tune(p, f0, steps=3, reps=1)
-    assert (best["drift_threads"], best["kick_rows"]) in V.tuning_candidates()
+    assert (best["drift_threads"], best["kick_rows"], best["kick_drift_width"]) in V.tuning_candidates()
     assert len(best["table"]) == len(V.tuning_candidates())
     assert autotune.tune(p, f0)["us_per_step"] == best["us_per_step"]  # served from the cache
