@@ -55,7 +55,7 @@ def algorithmic_bytes_per_point(kernel: str, s: int) -> float:
     as one drift: f once in, once out."""
     if kernel in ("drift", "drift2", "kick_drift2"):
         return 2 * s + 8.0 / 16.0
-    if kernel in ("kick", "kick_drift"):
+    if kernel == "kick":
         return 2.0 * s
     if kernel == "moments":
         return s + 4 * 8.0 / 16.0
@@ -273,7 +273,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=512, help="requests of the serving leg (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch shapes")
     ap.add_argument("--shape", default=None,
-                    help="fixed launch shape drift_threads/kick_rows/kick_drift_width (no autotuning)")
+                    help="fixed launch shape drift_threads/kick_rows/kick_drift_width/kick_drift_blocks "
+                         "(no autotuning)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -296,7 +297,7 @@ def main():
         from paper_1206_3229_amd import autotune
         pw, fw, _ = WORKLOADS[workload]()
         best = autotune.tune(pw, fw, use_cache=False)
-        return (best["drift_threads"], best["kick_rows"], best["kick_drift_width"]), best
+        return (best["drift_threads"], best["kick_rows"], best["kick_drift_width"], best["kick_drift_blocks"]), best
 
     shape, tuned = pick_shape(args.workload)
     p, secs, prof, mom, secs_events = run_gpu(args.workload, args.steps, args.warmup, torch, V, shape)
@@ -331,8 +332,10 @@ def main():
                      "bytes_per_point": bpp, "avg_launch_us": avg_s * 1e6, "launches": dom_n},
         "kernels_us": {k: (v[0] / v[1] * 1e3 if v[1] else None) for k, v in prof.items()},
         "launch_shape": {"drift_threads": shape[0], "kick_rows": shape[1], "kick_drift_width": shape[2],
+                         "kick_drift_blocks": shape[3],
                          "autotune_us_per_step": {
-                             f"{t['drift_threads']}/{t['kick_rows']}/{t['kick_drift_width']}": round(t["us_per_step"], 2)
+                             f"{t['drift_threads']}/{t['kick_rows']}/{t['kick_drift_width']}/{t['kick_drift_blocks']}":
+                                 round(t["us_per_step"], 2)
                              for t in tuned["table"]} if tuned else "fixed"} if shape else "default",
         "moments_end": {k: mom[k] for k in ("mass", "energy", "momentum")},
     }

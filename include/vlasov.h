@@ -164,15 +164,16 @@ const char *vlasov_last_error(void);
  * ------------------------------------------------------------------------- */
 
 typedef struct {
-    int32_t drift_threads;    /* threads per drift workgroup: 64, 128 or 256 (2 columns each) */
-    int32_t kick_rows;        /* rows per thread of the kick: 8, 16 or 32 */
-    int32_t kick_drift_width; /* 0: the kick (step 3) and the drift after it (step 4 and the next
-                                 step 1) run as separate kernels; 256 or 512: one fused kernel on
-                                 tiles of that many columns, which reads and writes f once for both
-                                 sweeps.  The fused kernel is used where the drift shifts of every
-                                 16-row block differ by at most 8 columns (4 per half drift when
-                                 two are fused), else the separate kernels run. */
-    int32_t reserved;         /* 0 */
+    int32_t drift_threads;     /* threads per drift workgroup: 64, 128 or 256 (2 columns each) */
+    int32_t kick_rows;         /* rows per thread of the kick: 8, 16 or 32 */
+    int32_t kick_drift_width;  /* 0: the kick (step 3) and the two half drifts after it (step 4
+                                  and the next step 1) run as separate kernels; 256 or 512: one
+                                  fused kernel on tiles of that many columns, which reads and
+                                  writes f once for both sweeps.  It is used where the drift
+                                  shifts of the rows of every tile differ by at most 4 columns,
+                                  else the separate kernels run.  The last step of a call
+                                  (kick and one half drift) always uses the separate kernels. */
+    int32_t kick_drift_blocks; /* rows of a fused tile in 16-row density blocks: 1, 2 or 4 */
 } vlasov_tuning;
 
 /* The compiled launch shapes: writes min(cap, total) of them, *n = total. */
@@ -180,7 +181,8 @@ int vlasov_tuning_candidates(vlasov_tuning *out, int32_t cap, int32_t *n);
 
 /* Select a compiled launch shape for a context (VLASOV_E_INVAL otherwise).
  * Defaults: 128 drift threads, 16 (FP64) or 32 (FP32) kick rows, fused kick
- * and drift on 512-column tiles. */
+ * and drift on tiles of 256 columns by 16 rows.  Changing kick_drift_blocks
+ * rebuilds the fused tables (synchronises the context's stream). */
 int vlasov_set_tuning(vlasov_ctx *c, const vlasov_tuning *t);
 int vlasov_get_tuning(vlasov_ctx *c, vlasov_tuning *t);
 
@@ -276,9 +278,8 @@ enum {
     VLASOV_K_FORCE = 3,    /* model force (and magnetization) */
     VLASOV_K_KICK = 4,     /* momentum advection */
     VLASOV_K_MOMENTS = 5,  /* diagnostics */
-    VLASOV_K_KICK_DRIFT = 6,   /* kick fused with one half drift */
-    VLASOV_K_KICK_DRIFT2 = 7,  /* kick fused with two half drifts + density partial sums */
-    VLASOV_K_COUNT = 8
+    VLASOV_K_KICK_DRIFT2 = 6,  /* kick fused with two half drifts + density partial sums */
+    VLASOV_K_COUNT = 7
 };
 
 /* When on, every kernel launch of the context is bracketed by HIP events on

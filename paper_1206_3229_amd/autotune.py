@@ -24,7 +24,7 @@ def cache_path() -> str:
 
 
 def _key(arch: str, p) -> str:
-    return f"{arch}|s{p.storage}|{p.nx}x{p.np_}|bc{p.bc_x}{p.bc_p}|dt{p.dt!r}|v2"
+    return f"{arch}|s{p.storage}|{p.nx}x{p.np_}|bc{p.bc_x}{p.bc_p}|dt{p.dt!r}|v3"
 
 
 def _load_cache() -> dict:
@@ -51,7 +51,7 @@ def _store(key: str, entry: dict):
 
 def tune(params, f0: np.ndarray, steps: int = 10, reps: int = 3, use_cache: bool = True) -> dict:
     """Best launch shape for this grid:
-    {"drift_threads", "kick_rows", "kick_drift_width", "us_per_step", "table"}."""
+    {"drift_threads", "kick_rows", "kick_drift_width", "kick_drift_blocks", "us_per_step", "table"}."""
     import torch
     arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName
     key = _key(arch, params)
@@ -61,8 +61,8 @@ def tune(params, f0: np.ndarray, steps: int = 10, reps: int = 3, use_cache: bool
             return hit
     s = V.Solver(params, f0)
     table = []
-    for nt, kr, kw in V.tuning_candidates():
-        s.set_tuning(nt, kr, kw)
+    for nt, kr, kw, kb in V.tuning_candidates():
+        s.set_tuning(nt, kr, kw, kb)
         s.step(2)
         times = []
         for _ in range(reps):
@@ -72,12 +72,12 @@ def tune(params, f0: np.ndarray, steps: int = 10, reps: int = 3, use_cache: bool
             e1.record()
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1) * 1e3 / steps)
-        table.append((float(np.median(times)), nt, kr, kw))
+        table.append((float(np.median(times)), nt, kr, kw, kb))
     s.close()
     table.sort()
     best = {"drift_threads": table[0][1], "kick_rows": table[0][2], "kick_drift_width": table[0][3],
-            "us_per_step": table[0][0],
-            "table": [{"drift_threads": nt, "kick_rows": kr, "kick_drift_width": kw, "us_per_step": t}
-                      for t, nt, kr, kw in table]}
+            "kick_drift_blocks": table[0][4], "us_per_step": table[0][0],
+            "table": [{"drift_threads": nt, "kick_rows": kr, "kick_drift_width": kw, "kick_drift_blocks": kb,
+                       "us_per_step": t} for t, nt, kr, kw, kb in table]}
     _store(key, best)
     return best

@@ -37,7 +37,7 @@ Layout layout_of(const vlasov_params &p)
     const size_t nx = (size_t)p.nx, np = (size_t)p.np;
     L.drift_m = take(np * sizeof(int32_t));
     L.drift_w = take(np * sizeof(double4));
-    L.kd_base = take(2 * (size_t)nblocks(p.np) * sizeof(int32_t));
+    L.kd_base = take((size_t)nblocks(p.np) * sizeof(int32_t));
     L.kd_rel = take(np * sizeof(int32_t));
     L.part = take((size_t)nblocks(p.np) * nx * sizeof(double));
     L.rho = take(nx * sizeof(double));
@@ -251,65 +251,108 @@ int kick(vlasov_ctx *c)
     return c->P.storage == VLASOV_F32 ? launch_kick<float>(c) : launch_kick<double>(c);
 }
 
-// Fused kick and drift (NPASS half drifts) with tile width TW.
-template <typename T, int TW>
-int launch_kick_drift_tw(vlasov_ctx *c, int npass, bool partials)
+// Fused kick and two half drifts (+ density partial sums) on tiles of TW
+// columns by RB density blocks.
+template <typename T, int TW, int RB>
+int launch_kick_drift_t(vlasov_ctx *c)
 {
     // whole wavefronts, about 5/8 TW threads: one first-pass run and up to two
     // kicked columns per thread
     constexpr int NT = (TW / 8 * 5 + 63) / 64 * 64;
     const vlasov_params &P = c->P;
-    const int ntx = (int)((P.nx + TW - 1) / TW), nty = (int)c->nblk;
+    const int ntx = (int)((P.nx + TW - 1) / TW), nty = (int)((c->nblk + RB - 1) / RB);
     const dim3 grid((unsigned)vk::xcd_grid(ntx, nty));
     const T *fin = (const T *)c->fcur();
     T *fout = (T *)c->fnext();
     const double *F = force_ptr(c);
     const int32_t *dm = c->at<int32_t>(c->L.drift_m);
     const double4 *dw = c->at<double4>(c->L.drift_w);
-    const int32_t *kbase = c->at<int32_t>(c->L.kd_base) + (size_t)(npass - 1) * c->nblk;
+    const int32_t *kbase = c->at<int32_t>(c->L.kd_base);
     const int32_t *krel = c->at<int32_t>(c->L.kd_rel);
     double *part = c->at<double>(c->L.part);
     const int nx = (int)P.nx, np = (int)P.np;
-    const int kid = npass == 2 ? VLASOV_K_KICK_DRIFT2 : VLASOV_K_KICK_DRIFT;
-#define KD_LAUNCH(NP, BX, BP, PT)                                                                                   \
-    launch(c, kid, vk::k_kick_drift<T, NP, BX, BP, PT, NT, TW, KD_PF>, grid, dim3(NT), fin, fout, F, P.dt, c->dp, dm, \
-           dw, kbase, krel, part, nx, np, ntx, nty)
-#define KD_BP(NP, BX, PT)                                                                                            \
-    do {                                                                                                             \
-        if (P.bc_p == VLASOV_BC_PERIODIC) KD_LAUNCH(NP, BX, vk::BC_PERIODIC, PT); else KD_LAUNCH(NP, BX, vk::BC_ZERO, PT); \
-    } while (0)
-#define KD_BX(NP, PT)                                                                                                \
-    do {                                                                                                             \
-        if (P.bc_x == VLASOV_BC_PERIODIC) KD_BP(NP, vk::BC_PERIODIC, PT); else KD_BP(NP, vk::BC_ZERO, PT);          \
-    } while (0)
-    if (npass == 2) {
-        if (partials) KD_BX(2, true); else KD_BX(2, false);
+#define KD_LAUNCH(BX, BP)                                                                                            \
+    launch(c, VLASOV_K_KICK_DRIFT2, vk::k_kick_drift<T, 2, BX, BP, true, NT, TW, KD_PF, RB>, grid, dim3(NT), fin, fout, \
+           F, P.dt, c->dp, dm, dw, kbase, krel, part, nx, np, ntx, nty)
+    if (P.bc_x == VLASOV_BC_PERIODIC) {
+        if (P.bc_p == VLASOV_BC_PERIODIC) KD_LAUNCH(vk::BC_PERIODIC, vk::BC_PERIODIC); else KD_LAUNCH(vk::BC_PERIODIC, vk::BC_ZERO);
     } else {
-        if (partials) KD_BX(1, true); else KD_BX(1, false);
+        if (P.bc_p == VLASOV_BC_PERIODIC) KD_LAUNCH(vk::BC_ZERO, vk::BC_PERIODIC); else KD_LAUNCH(vk::BC_ZERO, vk::BC_ZERO);
     }
-#undef KD_BX
-#undef KD_BP
 #undef KD_LAUNCH
     int rc = check_launch("kick+drift");
     if (rc == VLASOV_OK) c->cur ^= 1;
     return rc;
 }
 
-// Kick followed by NPASS half drifts: one fused kernel where the tables allow
-// it and the launch shape asks for it, else the two kernels.
+template <typename T, int TW>
+int launch_kick_drift_w(vlasov_ctx *c)
+{
+    switch (c->kd_rb) {
+    case 4:
+        return launch_kick_drift_t<T, TW, 4>(c);
+    case 2:
+        return launch_kick_drift_t<T, TW, 2>(c);
+    default:
+        return launch_kick_drift_t<T, TW, 1>(c);
+    }
+}
+
+// Kick followed by NPASS half drifts (+ partial sums for NPASS = 2): the
+// fused kernel for the pair of half drifts between two kicks where the
+// tables allow it and the launch shape asks for it, else the two kernels.
 int kick_then_drift(vlasov_ctx *c, int npass, bool partials)
 {
     const int w = c->tune.kick_drift_width;
-    if (w != 0 && c->kd_ok[npass - 1]) {
+    if (npass == 2 && partials && w != 0 && c->kd_ok) {
         const bool f32 = c->P.storage == VLASOV_F32;
-        if (w == 256) return f32 ? launch_kick_drift_tw<float, 256>(c, npass, partials)
-                                 : launch_kick_drift_tw<double, 256>(c, npass, partials);
-        return f32 ? launch_kick_drift_tw<float, 512>(c, npass, partials)
-                   : launch_kick_drift_tw<double, 512>(c, npass, partials);
+        if (w == 256) return f32 ? launch_kick_drift_w<float, 256>(c) : launch_kick_drift_w<double, 256>(c);
+        return f32 ? launch_kick_drift_w<float, 512>(c) : launch_kick_drift_w<double, 512>(c);
     }
     int rc = kick(c);
     if (rc == VLASOV_OK) rc = drift(c, npass, partials);
     return rc;
+}
+
+// Tables of the fused kick and drift for tiles of rb density blocks: per
+// tile the start of its kicked column range relative to the tile (two half
+// drifts), per row the offset of its window in that range.  Sets kd_ok.
+void build_kd_tables(vlasov_ctx *c, int rb)
+{
+    const vlasov_params &P = c->P;
+    const int64_t rows = (int64_t)vk::ROWS_PER_BLOCK * rb, ntile = (c->nblk + rb - 1) / rb;
+    c->h_kd_base.assign((size_t)c->nblk, 0);
+    c->h_kd_rel.assign((size_t)P.np, 0);
+    int64_t spread = 0;
+    for (int64_t b = 0; b < ntile; ++b) {
+        const int64_t j0 = b * rows, j1 = std::min<int64_t>(P.np, j0 + rows);
+        int64_t lo = c->h_mfull[j0], hi = lo;
+        for (int64_t j = j0; j < j1; ++j) {
+            lo = std::min(lo, c->h_mfull[j]);
+            hi = std::max(hi, c->h_mfull[j]);
+        }
+        spread = std::max(spread, hi - lo);
+        if (2 * (hi - lo) > vk::KD_SPR) continue;  // not fusable; the tables are unused
+        for (int64_t j = j0; j < j1; ++j) c->h_kd_rel[j] = (int32_t)(c->h_mfull[j] - lo);
+        int64_t s0 = 2 * lo - 8;
+        if (P.bc_x == VLASOV_BC_PERIODIC) {
+            s0 %= P.nx;
+            if (s0 < 0) s0 += P.nx;
+        }
+        c->h_kd_base[b] = (int32_t)s0;
+    }
+    c->kd_ok = 2 * spread <= vk::KD_SPR;
+    c->kd_rb = rb;
+}
+
+int upload_kd_tables(vlasov_ctx *c)
+{
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.kd_base, c->h_kd_base.data(), (size_t)c->nblk * sizeof(int32_t),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.kd_rel, c->h_kd_rel.data(), (size_t)c->P.np * sizeof(int32_t),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return VLASOV_OK;
 }
 
 void to_host_f(const vlasov_ctx *c, const void *src, double *dst)
@@ -382,7 +425,7 @@ int vlasov_init(const vlasov_params *p, const double *f0_host, void *f_dev, void
     c->tune.drift_threads = DRIFT_NT;
     c->tune.kick_rows = p->storage == VLASOV_F32 ? kick_rows<float>() : kick_rows<double>();
     c->tune.kick_drift_width = KD_TW;
-    c->tune.reserved = 0;
+    c->tune.kick_drift_blocks = KD_RB;
     for (int k = 0; k < VLASOV_K_COUNT; ++k) {
         c->ms[k] = 0.0;
         c->cnt[k] = 0;
@@ -392,44 +435,18 @@ int vlasov_init(const vlasov_params *p, const double *f0_host, void *f_dev, void
     const double tau = 0.5 * p->dt;
     c->h_dm.resize((size_t)p->np);
     c->h_dw.resize((size_t)p->np);
-    std::vector<int64_t> mfull((size_t)p->np);
+    c->h_mfull.resize((size_t)p->np);
     for (int64_t j = 0; j < p->np; ++j) {
         const double pj = p->pmin + (double)j * c->dp;
         const vk::Foot ft = vk::foot_of_shift((pj * tau) / c->dx);
         c->h_dm[j] = vk::reduce_offset(ft.m, p->nx, p->bc_x);
         c->h_dw[j] = make_double4(ft.a, ft.b, ft.g, ft.d);
         // offsets as the drift uses them: the exact foot on a periodic axis
-        // (the block's windows are then one contiguous range mod nx), the
+        // (the windows of a tile are then one contiguous range mod nx), the
         // clamped one with zero extension
-        mfull[j] = p->bc_x == VLASOV_BC_PERIODIC ? ft.m : (int64_t)c->h_dm[j];
+        c->h_mfull[j] = p->bc_x == VLASOV_BC_PERIODIC ? ft.m : (int64_t)c->h_dm[j];
     }
-    // Tables of the fused kick and drift: per block the start of the kicked
-    // range relative to the tile (for one and two half drifts), per row the
-    // offset of its window in that range.
-    c->h_kd_base.assign(2 * (size_t)c->nblk, 0);
-    c->h_kd_rel.assign((size_t)p->np, 0);
-    int64_t spread = 0;
-    for (int64_t b = 0; b < c->nblk; ++b) {
-        const int64_t j0 = b * vk::ROWS_PER_BLOCK, j1 = std::min<int64_t>(p->np, j0 + vk::ROWS_PER_BLOCK);
-        int64_t lo = mfull[j0], hi = mfull[j0];
-        for (int64_t j = j0; j < j1; ++j) {
-            lo = std::min(lo, mfull[j]);
-            hi = std::max(hi, mfull[j]);
-        }
-        spread = std::max(spread, hi - lo);
-        if (hi - lo > vk::KD_SPR) continue;  // not fusable; the tables are unused
-        for (int64_t j = j0; j < j1; ++j) c->h_kd_rel[j] = (int32_t)(mfull[j] - lo);
-        for (int np_ = 1; np_ <= 2; ++np_) {
-            int64_t s0 = np_ * lo - 4 * np_;
-            if (p->bc_x == VLASOV_BC_PERIODIC) {
-                s0 %= p->nx;
-                if (s0 < 0) s0 += p->nx;
-            }
-            c->h_kd_base[(size_t)(np_ - 1) * c->nblk + b] = (int32_t)s0;
-        }
-    }
-    c->kd_ok[0] = spread <= vk::KD_SPR;
-    c->kd_ok[1] = 2 * spread <= vk::KD_SPR;
+    build_kd_tables(c, c->tune.kick_drift_blocks);
     // Model tables.
     std::vector<double> cs((size_t)p->nx), sn((size_t)p->nx), K((size_t)p->nx, 0.0), V((size_t)p->nx, 0.0);
     for (int64_t i = 0; i < p->nx; ++i) {
@@ -472,7 +489,7 @@ int vlasov_init(const vlasov_params *p, const double *f0_host, void *f_dev, void
         size_t bytes;
     } ups[] = {{c->L.drift_m, c->h_dm.data(), (size_t)p->np * sizeof(int32_t)},
                {c->L.drift_w, c->h_dw.data(), (size_t)p->np * sizeof(double4)},
-               {c->L.kd_base, c->h_kd_base.data(), 2 * (size_t)c->nblk * sizeof(int32_t)},
+               {c->L.kd_base, c->h_kd_base.data(), (size_t)c->nblk * sizeof(int32_t)},
                {c->L.kd_rel, c->h_kd_rel.data(), (size_t)p->np * sizeof(int32_t)},
                {c->L.cs, cs.data(), nxb},
                {c->L.sn, sn.data(), nxb},
@@ -667,19 +684,20 @@ int vlasov_tuning_candidates(vlasov_tuning *out, int32_t cap, int32_t *n)
 {
     static const int nts[] = {64, 128, 256}, rs[] = {8, 16, 32};
     if (!n || cap < 0 || (cap > 0 && !out)) return fail(VLASOV_E_INVAL, "bad argument");
-    static const int kdw[] = {256, 512};
+    static const int kdw[] = {256, 512}, kdb[] = {1, 2, 4};
     int k = 0;
     for (int a : nts)
         for (int r : rs) {
-            if (k < cap) out[k] = vlasov_tuning{a, r, 0, 0};
+            if (k < cap) out[k] = vlasov_tuning{a, r, 0, 1};
             ++k;
         }
-    // fused kick and drift (the drift threads serve the first half drift of
-    // a call and grids that cannot fuse)
-    for (int w : kdw) {
-        if (k < cap) out[k] = vlasov_tuning{DRIFT_NT, kick_rows<double>(), w, 0};
-        ++k;
-    }
+    // fused kick and drift (the drift and kick shapes serve the first and last
+    // half drift of a call and grids that cannot fuse)
+    for (int w : kdw)
+        for (int b : kdb) {
+            if (k < cap) out[k] = vlasov_tuning{DRIFT_NT, kick_rows<double>(), w, b};
+            ++k;
+        }
     *n = k;
     return VLASOV_OK;
 }
@@ -690,8 +708,15 @@ int vlasov_set_tuning(vlasov_ctx *c, const vlasov_tuning *t)
     const bool nt_ok = t->drift_threads == 64 || t->drift_threads == 128 || t->drift_threads == 256;
     const bool r_ok = t->kick_rows == 8 || t->kick_rows == 16 || t->kick_rows == 32;
     const bool w_ok = t->kick_drift_width == 0 || t->kick_drift_width == 256 || t->kick_drift_width == 512;
-    if (!nt_ok || !r_ok || !w_ok || t->reserved != 0) return fail(VLASOV_E_INVAL, "launch shape not compiled in");
+    const bool b_ok = t->kick_drift_blocks == 1 || t->kick_drift_blocks == 2 || t->kick_drift_blocks == 4;
+    if (!nt_ok || !r_ok || !w_ok || !b_ok) return fail(VLASOV_E_INVAL, "launch shape not compiled in");
+    const bool retable = t->kick_drift_blocks != c->kd_rb;
     c->tune = *t;
+    if (retable) {
+        HIP_TRY(hipStreamSynchronize(c->stream));  // no kernel may read the tables being replaced
+        build_kd_tables(c, t->kick_drift_blocks);
+        return upload_kd_tables(c);
+    }
     return VLASOV_OK;
 }
 
@@ -735,8 +760,7 @@ int vlasov_profile_read(vlasov_ctx *c, int32_t kernel, double *total_ms, int64_t
 
 const char *vlasov_kernel_name(int32_t kernel)
 {
-    static const char *names[VLASOV_K_COUNT] = {"drift", "drift2",  "density",    "force",
-                                                "kick",  "moments", "kick_drift", "kick_drift2"};
+    static const char *names[VLASOV_K_COUNT] = {"drift", "drift2", "density", "force", "kick", "moments", "kick_drift2"};
     return (kernel >= 0 && kernel < VLASOV_K_COUNT) ? names[kernel] : "";
 }
 

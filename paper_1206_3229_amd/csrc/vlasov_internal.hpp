@@ -34,7 +34,7 @@ constexpr int DRIFT_NT = 128, DRIFT_V = 2, DRIFT_PF = 4;
 // kick rows per thread (measured best on 4096^2: 16 for FP64, 32 for FP32)
 template <typename T> constexpr int kick_rows() { return sizeof(T) == 8 ? 16 : 32; }
 // fused kick and drift: default tile width, rows requested ahead by the kick
-constexpr int KD_TW = 512, KD_PF = 4;
+constexpr int KD_TW = 256, KD_RB = 1, KD_PF = 4;
 
 // Workspace layout (byte offsets, each 256-aligned).
 struct Layout {
@@ -67,10 +67,12 @@ struct vlasov_ctx {
     // host copies kept alive for asynchronous uploads
     std::vector<int32_t> h_dm;
     std::vector<double4> h_dw;
+    std::vector<int64_t> h_mfull;  // drift foot offset per row, as the fused tables need it
     std::vector<int32_t> h_kd_base, h_kd_rel;
-    // kick and drift can run fused for NPASS = 1 / 2 (drift shifts of every
-    // 16-row block within the kicked halo)
-    bool kd_ok[2];
+    // kick and the two half drifts after it can run fused on tiles of
+    // kd_rb blocks (drift shifts of every tile within the kicked halo)
+    bool kd_ok;
+    int kd_rb;
     // profiling
     bool prof;
     struct Rec {

@@ -456,16 +456,18 @@ static __global__ __launch_bounds__(256) void k_kick(const T *__restrict__ fin, 
 // and written once for both sweeps.  The arithmetic of every value is that of
 // the separate kick and drift, so results are identical bit for bit.
 //
-// Tile: the 16 rows of one density block by TW output columns, NT threads.
-// The drift window of row j starts at column i0 + NPASS m_j - 4 NPASS; over
-// the block these windows lie in the KW = WIN + SPR kicked columns starting at
-// i0 + kbase (kbase = NPASS min_j m_j - 4 NPASS, reduced mod nx on a periodic
-// x axis), row j's window at offset NPASS krel_j, krel_j = m_j - min m.  A
-// grid whose blocks need NPASS krel > SPR takes the separate kernels.
-// Thread t kicks the columns kappa = t + k NT (k < KC) of that range, each
-// from a sliding window of the R + 10 samples of its column, requested PF
-// rows ahead, and writes the kicked row into the LDS window of the drift at
-// kappa - NPASS krel_j.
+// Tile: RB consecutive density blocks (16 RB rows) by TW output columns, NT
+// threads.  The drift window of row j starts at column i0 + NPASS m_j -
+// 4 NPASS; over the tile these windows lie in the KW = WIN + SPR kicked
+// columns starting at i0 + kbase (kbase = NPASS min_j m_j - 4 NPASS, reduced
+// mod nx on a periodic x axis), row j's window at offset NPASS krel_j, krel_j
+// = m_j - min m.  A grid whose tiles need NPASS krel > SPR takes the separate
+// kernels.  Thread t kicks the columns kappa = t + k NT (k < KC) of that
+// range, each from a sliding register window of its column (the kick of row
+// r needs the samples r - 4 + m .. r + 5 + m), requested PF rows ahead and
+// carried across the blocks of the tile, and writes the kicked row into the
+// LDS window of the drift at kappa - NPASS krel_j.  The taller the tile, the
+// smaller the share of the 10 halo rows the kick reads above and below it.
 // ---------------------------------------------------------------------------
 constexpr int KD_SPR = 8;
 
@@ -479,7 +481,7 @@ struct KickDriftGeom {
     static_assert(TW <= V * NT, "one output run per thread");
 };
 
-template <typename T, int NPASS, int BCX, int BCP, bool PARTIALS, int NT, int TW, int PF, bool FULL>
+template <typename T, int NPASS, int BCX, int BCP, bool PARTIALS, int NT, int TW, int PF, int RB, bool FULL>
 __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__restrict__ fout,
                                                 const double *__restrict__ F, double dt, double dp,
                                                 const int32_t *__restrict__ dm, const double4 *__restrict__ dw,
@@ -489,13 +491,14 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
 {
     using KG = KickDriftGeom<NPASS, NT, TW>;
     using G = typename KG::G;
-    constexpr int V = KG::V, KC = KG::KC, R = ROWS_PER_BLOCK, NS = R + 10;
+    constexpr int V = KG::V, KC = KG::KC, R = ROWS_PER_BLOCK;
+    constexpr int NS = R + 10 + PF;  // window slots: samples of a block plus those requested ahead
     constexpr int WIN = G::WIN, MIDN = G::MIDN, NRUN1 = G::NRUN1, LDW = G::LDW, LDM = G::LDM;
     static_assert(NS <= 32, "one mask bit per sample");
     const int t = threadIdx.x;
     const int i0 = tx * TW;
-    const int j0 = ty * R;
-    const int nr = FULL ? R : min(R, np - j0);
+    const int j0 = ty * (R * RB);
+    const int nr = FULL ? R * RB : min(R * RB, np - j0);  // rows of the tile
 
     for (int s = WIN + t; s < LDW; s += NT) {
         win0[s] = T(0);
@@ -508,7 +511,7 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
     // sample row, and masks of the samples that lie inside the grid.
     const int cL = i0 + kbase[ty];
     const T *colp[KC];
-    int rbase[KC];
+    int rbase[KC];  // row of sample 0 of the current block (wrapped or unclamped)
     uint32_t inside[KC];
     bool colin[KC];
     T ka[KC], kb[KC], kg[KC], kd[KC];
@@ -532,12 +535,13 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
         kd[k] = (T)ft.d;
         colp[k] = fin + gc;
         int b = j0 + m - 4;
-        if (BCP == BC_PERIODIC) b = b >= np ? b - np : (b < 0 ? b + np : b);
+        if (BCP == BC_PERIODIC) b = wrap(b, np);
         rbase[k] = b;
         inside[k] = 0;
     }
-    // Sample s of column k: row rbase + s, wrapped or clamped (zero rows are
-    // masked when the sample is first used, never next to its load).
+    // Sample s of column k in the current block: row rbase + s, wrapped or
+    // clamped (zero rows are masked when the sample is first used, never next
+    // to its load).  rbase < np and s < NS <= 32 <= 2 np, so two wraps suffice.
     T w[KC][NS];
     auto request = [&](int s) {
 #pragma unroll
@@ -569,77 +573,95 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
 
     const int i = i0 + V * t;
     const bool own = FULL ? V * t < TW : (V * t < TW && i < nx);
-    double acc[V];
+#pragma unroll 1
+    for (int blk = 0; blk < RB; ++blk) {
+        const int jb = j0 + R * blk;
+        if (!FULL && R * blk >= nr) break;  // uniform
+        double acc[V];
 #pragma unroll
-    for (int k = 0; k < V; ++k) acc[k] = 0.0;
+        for (int k = 0; k < V; ++k) acc[k] = 0.0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (FULL || r < nr) {
-            const int j = j0 + r;
-            T *wrow = (r & 1) ? win1 : win0;
-            settle(r + 9);
-            const int rel = NPASS * krel[j];
+        for (int r = 0; r < R; ++r) {
+            if (FULL || R * blk + r < nr) {
+                const int j = jb + r;
+                T *wrow = (r & 1) ? win1 : win0;
+                settle(r + 9);
+                const int rel = NPASS * krel[j];
 #pragma unroll
-            for (int k = 0; k < KC; ++k) {
-                const T Dk1 = second_diff(w[k] + r + 5);
-                T y = spline(ka[k], kb[k], kg[k], kd[k], w[k][r + 4], w[k][r + 5], Dk[k], Dk1);
-                Dk[k] = Dk1;
-                if (BCX != BC_PERIODIC) y = colin[k] ? y : T(0);
-                const int pos = t + k * NT - rel;
-                wrow[(unsigned)pos < (unsigned)WIN ? pos : LDW] = y;
-            }
-            if (r + 10 + PF < NS) request(r + 10 + PF);
-            __syncthreads();
-            const double4 wd = dw[j];
-            const T a = (T)wd.x, b = (T)wd.y, g = (T)wd.z, d = (T)wd.w;
-            const T *src = wrow;
-            if (NPASS == 2) {
-                // first half drift at positions i0 + m - 4 + q, q in [0, TW + 9)
-                const int m = dm[j];
-                if (t < NRUN1) {
+                for (int k = 0; k < KC; ++k) {
+                    const T Dk1 = second_diff(w[k] + r + 5);
+                    T y = spline(ka[k], kb[k], kg[k], kd[k], w[k][r + 4], w[k][r + 5], Dk[k], Dk1);
+                    Dk[k] = Dk1;
+                    if (BCX != BC_PERIODIC) y = colin[k] ? y : T(0);
+                    const int pos = t + k * NT - rel;
+                    wrow[(unsigned)pos < (unsigned)WIN ? pos : LDW] = y;
+                }
+                // the samples of the next block are requested too (clamped
+                // or wrapped addresses; unused after the last block)
+                if (r + 10 + PF < NS && (RB > 1 || r + 10 + PF < R + 10)) request(r + 10 + PF);
+                __syncthreads();
+                const double4 wd = dw[j];
+                const T a = (T)wd.x, b = (T)wd.y, g = (T)wd.z, d = (T)wd.w;
+                const T *src = wrow;
+                if (NPASS == 2) {
+                    // first half drift at positions i0 + m - 4 + q, q in [0, TW + 9)
+                    const int m = dm[j];
+                    if (t < NRUN1) {
+                        T o[V];
+                        spline_run<T, V>(src, t, a, b, g, d, o);
+                        if (BCX == BC_ZERO) {
+                            const int q = i0 + m - 4 + V * t;
+#pragma unroll
+                            for (int k = 0; k < V; ++k)
+                                if (q + k < 0 || q + k >= nx) o[k] = T(0);
+                        }
+                        typename Vec2<T>::type ww;
+                        ww.x = o[0];
+                        ww.y = o[1];
+                        reinterpret_cast<typename Vec2<T>::type *>(mid)[t] = ww;
+                    }
+                    __syncthreads();
+                    src = mid;
+                }
+                if (own) {
                     T o[V];
                     spline_run<T, V>(src, t, a, b, g, d, o);
-                    if (BCX == BC_ZERO) {
-                        const int q = i0 + m - 4 + V * t;
-#pragma unroll
-                        for (int k = 0; k < V; ++k)
-                            if (q + k < 0 || q + k >= nx) o[k] = T(0);
+                    if (FULL) {
+                        typename Vec2<T>::type ww;
+                        ww.x = o[0];
+                        ww.y = o[1];
+                        *reinterpret_cast<typename Vec2<T>::type *>(fout + (size_t)j * nx + i) = ww;
+                    } else {
+                        store_run<T, V>(fout + (size_t)j * nx, i, nx, o);
                     }
-                    typename Vec2<T>::type ww;
-                    ww.x = o[0];
-                    ww.y = o[1];
-                    reinterpret_cast<typename Vec2<T>::type *>(mid)[t] = ww;
-                }
-                __syncthreads();
-                src = mid;
-            }
-            if (own) {
-                T o[V];
-                spline_run<T, V>(src, t, a, b, g, d, o);
-                if (FULL) {
-                    typename Vec2<T>::type ww;
-                    ww.x = o[0];
-                    ww.y = o[1];
-                    *reinterpret_cast<typename Vec2<T>::type *>(fout + (size_t)j * nx + i) = ww;
-                } else {
-                    store_run<T, V>(fout + (size_t)j * nx, i, nx, o);
-                }
-                if (PARTIALS) {
+                    if (PARTIALS) {
 #pragma unroll
-                    for (int k = 0; k < V; ++k) acc[k] = acc[k] + (double)o[k];
+                        for (int k = 0; k < V; ++k) acc[k] = acc[k] + (double)o[k];
+                    }
                 }
             }
         }
-    }
-    if (PARTIALS && own) {
-        double *prow = part + (size_t)ty * nx;
+        if (PARTIALS && own) {
+            double *prow = part + (size_t)(ty * RB + blk) * nx;
 #pragma unroll
-        for (int k = 0; k < V; ++k)
-            if (FULL || i + k < nx) prow[i + k] = acc[k];
+            for (int k = 0; k < V; ++k)
+                if (FULL || i + k < nx) prow[i + k] = acc[k];
+        }
+        // slide the windows by one block: sample s + 16 becomes sample s
+        if (RB > 1) {
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+#pragma unroll
+                for (int s = 0; s + R < NS; ++s) w[k][s] = w[k][s + R];
+                inside[k] >>= R;
+                rbase[k] += R;
+                if (BCP == BC_PERIODIC) rbase[k] = rbase[k] >= np ? rbase[k] - np : rbase[k];
+            }
+        }
     }
 }
 
-template <typename T, int NPASS, int BCX, int BCP, bool PARTIALS, int NT, int TW, int PF>
+template <typename T, int NPASS, int BCX, int BCP, bool PARTIALS, int NT, int TW, int PF, int RB>
 static __global__ __launch_bounds__(NT) void k_kick_drift(const T *__restrict__ fin, T *__restrict__ fout,
                                                    const double *__restrict__ F, double dt, double dp,
                                                    const int32_t *__restrict__ dm,
@@ -653,13 +675,13 @@ static __global__ __launch_bounds__(NT) void k_kick_drift(const T *__restrict__ 
     __shared__ __attribute__((aligned(16))) T mid[G::LDM];
     int tx, ty;
     if (!xcd_tile(ntx, nty, tx, ty)) return;
-    const bool full = (ty + 1) * ROWS_PER_BLOCK <= np && (tx + 1) * TW <= nx && (nx & 1) == 0;
+    const bool full = (ty + 1) * (ROWS_PER_BLOCK * RB) <= np && (tx + 1) * TW <= nx && (nx & 1) == 0;
     if (full)
-        kick_drift_tile<T, NPASS, BCX, BCP, PARTIALS, NT, TW, PF, true>(fin, fout, F, dt, dp, dm, dw, kbase, krel,
-                                                                        part, nx, np, tx, ty, win[0], win[1], mid);
+        kick_drift_tile<T, NPASS, BCX, BCP, PARTIALS, NT, TW, PF, RB, true>(fin, fout, F, dt, dp, dm, dw, kbase, krel,
+                                                                            part, nx, np, tx, ty, win[0], win[1], mid);
     else
-        kick_drift_tile<T, NPASS, BCX, BCP, PARTIALS, NT, TW, PF, false>(fin, fout, F, dt, dp, dm, dw, kbase, krel,
-                                                                         part, nx, np, tx, ty, win[0], win[1], mid);
+        kick_drift_tile<T, NPASS, BCX, BCP, PARTIALS, NT, TW, PF, RB, false>(fin, fout, F, dt, dp, dm, dw, kbase, krel,
+                                                                             part, nx, np, tx, ty, win[0], win[1], mid);
 }
 
 // ---------------------------------------------------------------------------

@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(PKG, "libvlasov.so")
 OK, PENDING = 0, 1
 E_INVAL, E_NOMEM, E_HIP, E_STATE, E_NOTFOUND, E_NONFINITE = -1, -2, -3, -4, -5, -6
 
-K_DRIFT, K_DRIFT2, K_DENSITY, K_FORCE, K_KICK, K_MOMENTS, K_KICK_DRIFT, K_KICK_DRIFT2 = range(8)
-KERNELS = ("drift", "drift2", "density", "force", "kick", "moments", "kick_drift", "kick_drift2")
+K_DRIFT, K_DRIFT2, K_DENSITY, K_FORCE, K_KICK, K_MOMENTS, K_KICK_DRIFT2 = range(7)
+KERNELS = ("drift", "drift2", "density", "force", "kick", "moments", "kick_drift2")
 
 
 class VlasovError(RuntimeError):
@@ -45,7 +45,7 @@ class Moments(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("drift_threads", C.c_int32), ("kick_rows", C.c_int32), ("kick_drift_width", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("kick_drift_blocks", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -216,16 +216,17 @@ class Solver:
         return np.stack([mx[:k], my[:k]], axis=1)
 
     # -- launch shapes ---------------------------------------------------
-    def set_tuning(self, drift_threads: int, kick_rows: int, kick_drift_width: int = 0):
+    def set_tuning(self, drift_threads: int, kick_rows: int, kick_drift_width: int = 0, kick_drift_blocks: int = 1):
         """kick_drift_width 0: separate kick and drift kernels; 256 or 512:
-        the fused kernel on tiles of that width (where the grid allows it)."""
-        t = Tuning(int(drift_threads), int(kick_rows), int(kick_drift_width), 0)
+        the fused kernel on tiles of that width and kick_drift_blocks 16-row
+        blocks (where the grid allows it)."""
+        t = Tuning(int(drift_threads), int(kick_rows), int(kick_drift_width), int(kick_drift_blocks))
         check(load().vlasov_set_tuning(self._ctx, C.byref(t)))
 
-    def get_tuning(self) -> tuple[int, int, int]:
+    def get_tuning(self) -> tuple[int, int, int, int]:
         t = Tuning()
         check(load().vlasov_get_tuning(self._ctx, C.byref(t)))
-        return t.drift_threads, t.kick_rows, t.kick_drift_width
+        return t.drift_threads, t.kick_rows, t.kick_drift_width, t.kick_drift_blocks
 
     # -- measurement -----------------------------------------------------
     def profile(self, on: bool = True):
@@ -325,13 +326,13 @@ class Server:
             pass
 
 
-def tuning_candidates() -> list[tuple[int, int, int]]:
-    """(drift_threads, kick_rows, kick_drift_width) of every compiled shape."""
+def tuning_candidates() -> list[tuple[int, int, int, int]]:
+    """(drift_threads, kick_rows, kick_drift_width, kick_drift_blocks) of every compiled shape."""
     n = C.c_int32()
     check(load().vlasov_tuning_candidates(None, 0, C.byref(n)))
     arr = (Tuning * n.value)()
     check(load().vlasov_tuning_candidates(arr, n.value, C.byref(n)))
-    return [(t.drift_threads, t.kick_rows, t.kick_drift_width) for t in arr]
+    return [(t.drift_threads, t.kick_rows, t.kick_drift_width, t.kick_drift_blocks) for t in arr]
 
 
 def request_footprint(params) -> int:

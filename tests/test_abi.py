@@ -79,13 +79,14 @@ def test_null_and_misaligned_pointers_rejected(lib):
 
 
 def test_kernel_names(lib):
-    assert [lib.vlasov_kernel_name(k).decode() for k in range(9)] == \
-        ["drift", "drift2", "density", "force", "kick", "moments", "kick_drift", "kick_drift2", ""]
+    assert [lib.vlasov_kernel_name(k).decode() for k in range(8)] == \
+        ["drift", "drift2", "density", "force", "kick", "moments", "kick_drift2", ""]
 
 
 def test_tuning_candidates_cover_separate_and_fused(lib):
     from paper_1206_3229_amd import vlasov as V
     cands = V.tuning_candidates()
-    assert len(cands) == len(set(cands)) == 11
+    assert len(cands) == len(set(cands)) == 15
     assert sum(1 for c in cands if c[2] == 0) == 9
     assert {c[2] for c in cands} == {0, 256, 512}
+    assert {(c[2], c[3]) for c in cands if c[2]} == {(w, b) for w in (256, 512) for b in (1, 2, 4)}

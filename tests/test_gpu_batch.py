@@ -160,12 +160,14 @@ def test_every_launch_shape_gives_identical_results(V):
         if ref is None:
             ref = f
         assert np.array_equal(f, ref), shape
-    assert {w for _, _, w in V.tuning_candidates()} == {0, 256, 512}
+    assert {c[2] for c in V.tuning_candidates()} == {0, 256, 512}
     s = V.Solver(p, f0)
     with pytest.raises(V.VlasovError):
         s.set_tuning(96, 16)
     with pytest.raises(V.VlasovError):
         s.set_tuning(128, 16, 384)
+    with pytest.raises(V.VlasovError):
+        s.set_tuning(128, 16, 256, 3)
     s.close()
 
 
@@ -174,6 +176,7 @@ def test_autotune_picks_a_compiled_shape(V, tmp_path, monkeypatch):
     monkeypatch.setenv("VLASOV_TUNE_CACHE", str(tmp_path / "tune.json"))
     p, f0, _ = I.hmf_waterbag_small()
     best = autotune.tune(p, f0, steps=3, reps=1)
-    assert (best["drift_threads"], best["kick_rows"], best["kick_drift_width"]) in V.tuning_candidates()
+    assert (best["drift_threads"], best["kick_rows"], best["kick_drift_width"],
+            best["kick_drift_blocks"]) in V.tuning_candidates()
     assert len(best["table"]) == len(V.tuning_candidates())
     assert autotune.tune(p, f0)["us_per_step"] == best["us_per_step"]  # served from the cache

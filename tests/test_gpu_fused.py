@@ -1,8 +1,8 @@
-"""The kick fused with the drift after it: every tile width gives the same
-bits as the separate kick and drift kernels and as the oracle, on ragged
-grids, both boundary rules on each axis, both storage types, and grids whose
-drift shifts are too far apart within a 16-row block to fuse (those fall back
-to the separate kernels)."""
+"""The kick fused with the two half drifts after it: every tile shape gives
+the same bits as the separate kick and drift kernels and as the oracle, on
+ragged grids, both boundary rules on each axis, both storage types, and grids
+whose drift shifts are too far apart within a tile to fuse (those fall back to
+the separate kernels)."""
 import math
 
 import numpy as np
@@ -12,7 +12,8 @@ from paper_1206_3229_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-WIDTHS = (0, 256, 512)
+# (kick_drift_width, kick_drift_blocks)
+SHAPES = ((0, 1), (256, 1), (256, 2), (256, 4), (512, 1), (512, 4))
 
 
 @pytest.fixture(scope="module")
@@ -55,11 +56,11 @@ CASES = {
 }
 
 
-def block_spread(p):
-    """Largest difference of the drift offsets (cells) within a 16-row block:
-    the foot m_j = floor(-p_j (dt/2)/dx) of each row, clamped to +-(nx + 16)
-    with zero extension in x.  Kick and drift fuse for NPASS half drifts when
-    NPASS * spread <= 8."""
+def block_spread(p, rb=1):
+    """Largest difference of the drift offsets (cells) within a tile of rb
+    16-row blocks: the foot m_j = floor(-p_j (dt/2)/dx) of each row, clamped
+    to +-(nx + 16) with zero extension in x.  Kick and the two half drifts
+    after it fuse when 2 * spread <= 8."""
     dx, dp, tau = p.dx, p.dp, 0.5 * p.dt
     ms = []
     for j in range(p.np_):
@@ -70,12 +71,14 @@ def block_spread(p):
         if p.bc_x == I.BC_ZERO:
             m = max(-(p.nx + 16), min(p.nx + 16, m))
         ms.append(m)
-    return max(max(ms[b:b + 16]) - min(ms[b:b + 16]) for b in range(0, p.np_, 16))
+    rows = 16 * rb
+    return max(max(ms[b:b + rows]) - min(ms[b:b + rows]) for b in range(0, p.np_, rows))
 
 
 def test_cases_cover_fused_and_fallback_paths():
     spreads = {k: block_spread(p) for k, (p, _) in CASES.items()}
     assert sum(2 * s <= 8 for s in spreads.values()) >= 8
+    assert sum(2 * block_spread(p, 4) <= 8 for p, _ in CASES.values()) >= 6
     assert spreads["hmf_zero_p_spread4"] == 4
     assert 4 < spreads["hmf_mid_shift"] <= 8
     assert spreads["hmf_large_shift"] > 8
@@ -88,9 +91,9 @@ def _ic(p, seed=1):
     return I.waterbag(p, th0, p0, 1e-4, seed)
 
 
-def _run(V, p, f0, n, width):
+def _run(V, p, f0, n, width, blocks):
     s = V.Solver(p, f0, hist_cap=n)
-    s.set_tuning(128, 16, width)
+    s.set_tuning(128, 16, width, blocks)
     s.profile(True)
     s.step(n)
     prof = s.profile_read()
@@ -102,34 +105,45 @@ def _run(V, p, f0, n, width):
 @pytest.mark.parametrize("name", list(CASES))
 def test_fused_equals_separate_and_oracle(V, oracle, name):
     p, n = CASES[name]
-    fuses = 2 * block_spread(p) <= 8
     f0 = _ic(p)
     _log(f"fused {name}: {p.nx}x{p.np_} bc {p.bc_x}{p.bc_p} storage {p.storage}, {n} steps")
-    runs = {w: _run(V, p, f0, n, w) for w in WIDTHS}
     want, hist_want = oracle.run(p, f0, n, history=True)
-    for w, (f, hist, prof) in runs.items():
-        assert np.array_equal(f, want, equal_nan=True), (name, w, float(np.nanmax(np.abs(f - want))))
+    for w, b in SHAPES:
+        f, hist, prof = _run(V, p, f0, n, w, b)
+        assert np.array_equal(f, want, equal_nan=True), (name, w, b, float(np.nanmax(np.abs(f - want))))
         if p.model in (I.MODEL_HMF, I.MODEL_RING):
-            assert np.array_equal(hist, hist_want), (name, w)
-        fused2 = prof["kick_drift2"][1]
-        if w == 0 or not fuses:
-            assert fused2 == 0, (name, w)
-            assert prof["kick"][1] + prof["kick_drift"][1] == n
+            assert np.array_equal(hist, hist_want), (name, w, b)
+        fused = w != 0 and 2 * block_spread(p, b) <= 8
+        if fused:
+            assert prof["kick_drift2"][1] == n - 1 and prof["kick"][1] == 1, (name, w, b, prof)
         else:
-            assert fused2 == n - 1 and prof["kick"][1] == 0, (name, w, prof)
+            assert prof["kick_drift2"][1] == 0 and prof["kick"][1] == n, (name, w, b, prof)
 
 
-def test_fused_single_step_and_split_calls(V, oracle):
-    # one step per call: only the last-step form (kick + one half drift)
+def test_fused_single_step_calls(V, oracle):
+    # one step per call: only the last-step form (kick + one half drift), which
+    # runs as separate kernels; results are those of one four-step call
     p = _sheet(300, 40, dt=0.04)
     f0 = _ic(p)
     s = V.Solver(p, f0)
-    s.set_tuning(128, 16, 512)
+    s.set_tuning(128, 16, 512, 2)
     s.profile(True)
     for _ in range(4):
         s.step(1)
     prof = s.profile_read()
     got = s.read_f()
     s.close()
-    assert prof["kick_drift"][1] == 4 and prof["kick_drift2"][1] == 0
+    assert prof["kick_drift2"][1] == 0 and prof["kick"][1] == 4
     assert np.array_equal(got, oracle.run(p, f0, 4))
+
+
+def test_fused_tile_heights_on_a_ragged_grid(V, oracle):
+    # 77 rows: tiles of 4 blocks leave a last tile of 13 rows
+    p = _hmf(530, 77, dt=0.01)
+    f0 = _ic(p, seed=4)
+    want = oracle.run(p, f0, 5)
+    assert 2 * block_spread(p, 4) <= 8
+    for w, b in SHAPES:
+        f, _, prof = _run(V, p, f0, 5, w, b)
+        assert np.array_equal(f, want), (w, b)
+        assert prof["kick_drift2"][1] == (4 if w else 0)
