@@ -471,9 +471,9 @@ static __global__ __launch_bounds__(256) void k_kick(const T *__restrict__ fin, 
 // ---------------------------------------------------------------------------
 constexpr int KD_SPR = 8;
 
-template <int NPASS, int NT, int TW>
+template <int NPASS, int NT, int TW, int VR = 2>
 struct KickDriftGeom {
-    static constexpr int V = 2;
+    static constexpr int V = VR;  // adjacent outputs per thread in the half drifts
     using G = DriftGeom<NPASS, NT, V, V * NT - TW>;
     static constexpr int KW = G::WIN + KD_SPR;      // kicked columns per row
     static constexpr int KC = (KW + NT - 1) / NT;  // kicked columns per thread
@@ -481,7 +481,8 @@ struct KickDriftGeom {
     static_assert(TW <= V * NT, "one output run per thread");
 };
 
-template <typename T, int NPASS, int BCX, int BCP, bool PARTIALS, int NT, int TW, int PF, int RB, bool FULL>
+template <typename T, int NPASS, int BCX, int BCP, bool PARTIALS, int NT, int TW, int PF, int RB, int VR, int UB,
+          bool FULL>
 __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__restrict__ fout,
                                                 const double *__restrict__ F, double dt, double dp,
                                                 const int32_t *__restrict__ dm, const double4 *__restrict__ dw,
@@ -489,7 +490,7 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
                                                 double *__restrict__ part, int nx, int np, int tx, int ty, T *win0,
                                                 T *win1, T *mid)
 {
-    using KG = KickDriftGeom<NPASS, NT, TW>;
+    using KG = KickDriftGeom<NPASS, NT, TW, VR>;
     using G = typename KG::G;
     constexpr int V = KG::V, KC = KG::KC, R = ROWS_PER_BLOCK;
     constexpr int NS = R + 10 + PF;  // window slots: samples of a block plus those requested ahead
@@ -573,7 +574,8 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
 
     const int i = i0 + V * t;
     const bool own = FULL ? V * t < TW : (V * t < TW && i < nx);
-#pragma unroll 1
+    // UB = RB unrolls the blocks (the window slide becomes register renaming)
+#pragma unroll UB
     for (int blk = 0; blk < RB; ++blk) {
         const int jb = j0 + R * blk;
         if (!FULL && R * blk >= nr) break;  // uniform
@@ -615,10 +617,13 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
                             for (int k = 0; k < V; ++k)
                                 if (q + k < 0 || q + k >= nx) o[k] = T(0);
                         }
-                        typename Vec2<T>::type ww;
-                        ww.x = o[0];
-                        ww.y = o[1];
-                        reinterpret_cast<typename Vec2<T>::type *>(mid)[t] = ww;
+#pragma unroll
+                        for (int k = 0; k < V; k += 2) {
+                            typename Vec2<T>::type ww;
+                            ww.x = o[k];
+                            ww.y = o[k + 1];
+                            reinterpret_cast<typename Vec2<T>::type *>(mid + V * t)[k / 2] = ww;
+                        }
                     }
                     __syncthreads();
                     src = mid;
@@ -627,10 +632,13 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
                     T o[V];
                     spline_run<T, V>(src, t, a, b, g, d, o);
                     if (FULL) {
-                        typename Vec2<T>::type ww;
-                        ww.x = o[0];
-                        ww.y = o[1];
-                        *reinterpret_cast<typename Vec2<T>::type *>(fout + (size_t)j * nx + i) = ww;
+#pragma unroll
+                        for (int k = 0; k < V; k += 2) {
+                            typename Vec2<T>::type ww;
+                            ww.x = o[k];
+                            ww.y = o[k + 1];
+                            *reinterpret_cast<typename Vec2<T>::type *>(fout + (size_t)j * nx + i + k) = ww;
+                        }
                     } else {
                         store_run<T, V>(fout + (size_t)j * nx, i, nx, o);
                     }
@@ -661,7 +669,8 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
     }
 }
 
-template <typename T, int NPASS, int BCX, int BCP, bool PARTIALS, int NT, int TW, int PF, int RB>
+template <typename T, int NPASS, int BCX, int BCP, bool PARTIALS, int NT, int TW, int PF, int RB, int VR = 2,
+          int UB = 1>
 static __global__ __launch_bounds__(NT) void k_kick_drift(const T *__restrict__ fin, T *__restrict__ fout,
                                                    const double *__restrict__ F, double dt, double dp,
                                                    const int32_t *__restrict__ dm,
@@ -670,18 +679,18 @@ static __global__ __launch_bounds__(NT) void k_kick_drift(const T *__restrict__ 
                                                    const int32_t *__restrict__ krel, double *__restrict__ part,
                                                    int nx, int np, int ntx, int nty)
 {
-    using G = typename KickDriftGeom<NPASS, NT, TW>::G;
+    using G = typename KickDriftGeom<NPASS, NT, TW, VR>::G;
     __shared__ __attribute__((aligned(16))) T win[2][G::LDA];
     __shared__ __attribute__((aligned(16))) T mid[G::LDM];
     int tx, ty;
     if (!xcd_tile(ntx, nty, tx, ty)) return;
     const bool full = (ty + 1) * (ROWS_PER_BLOCK * RB) <= np && (tx + 1) * TW <= nx && (nx & 1) == 0;
     if (full)
-        kick_drift_tile<T, NPASS, BCX, BCP, PARTIALS, NT, TW, PF, RB, true>(fin, fout, F, dt, dp, dm, dw, kbase, krel,
-                                                                            part, nx, np, tx, ty, win[0], win[1], mid);
+        kick_drift_tile<T, NPASS, BCX, BCP, PARTIALS, NT, TW, PF, RB, VR, UB, true>(
+            fin, fout, F, dt, dp, dm, dw, kbase, krel, part, nx, np, tx, ty, win[0], win[1], mid);
     else
-        kick_drift_tile<T, NPASS, BCX, BCP, PARTIALS, NT, TW, PF, RB, false>(fin, fout, F, dt, dp, dm, dw, kbase, krel,
-                                                                             part, nx, np, tx, ty, win[0], win[1], mid);
+        kick_drift_tile<T, NPASS, BCX, BCP, PARTIALS, NT, TW, PF, RB, VR, UB, false>(
+            fin, fout, F, dt, dp, dm, dw, kbase, krel, part, nx, np, tx, ty, win[0], win[1], mid);
 }
 
 // ---------------------------------------------------------------------------

@@ -41,6 +41,12 @@ def mixed_cases(storage):
     out.append((p, I.waterbag(p, th0, p0, 1e-4, 4), 0, None))
     p = I.Params(I.MODEL_HMF, 64, 512, -math.pi, math.pi, -2.5, 2.5, 0.05, storage=storage)
     out.append((p, I.gaussian(p, 0.4, 1e-3), 9, None))
+    # wider grids: several drift tiles per row, both zero boundaries
+    p = I.Params(I.MODEL_HMF, 1024, 40, -math.pi, math.pi, -2.5, 2.5, 0.01, storage=storage)
+    out.append((p, I.waterbag(p, th0, p0, 1e-4, 6), 8, None))
+    p = I.Params(I.MODEL_SHEET, 500, 37, -10.0, 10.0, -4.0, 4.0, 0.02, bc_x=I.BC_ZERO, bc_p=I.BC_ZERO,
+                 storage=storage)
+    out.append((p, I.waterbag(p, 1.0, 0.5, 1e-4, 7), 6, None))
     return out
 
 
