@@ -58,7 +58,7 @@ def algorithmic_bytes_per_point(kernel: str, s: int) -> float:
     if kernel == "kick":
         return 2.0 * s
     if kernel == "moments":
-        return s + 4 * 8.0 / 16.0
+        return 2 * s + 6 * 8.0 / 16.0
     return float("nan")
 
 

@@ -133,13 +133,13 @@ def force(p, rho: np.ndarray, F_ext=None):
     return F, (float(mm[0]), float(mm[1]))
 
 
-MOMENT_NAMES = ("mass", "momentum", "kinetic", "potential", "energy", "mx", "my", "l2")
+MOMENT_NAMES = ("mass", "momentum", "kinetic", "potential", "energy", "mx", "my", "l2", "entropy", "neg_mass")
 
 
 def moments(p, f: np.ndarray) -> dict:
     lib = _load()
     f = _f64(f)
-    out = np.zeros(8)
+    out = np.zeros(len(MOMENT_NAMES))
     lib.oracle_moments(C.byref(_params(p)), _ptr(f), _ptr(out))
     return dict(zip(MOMENT_NAMES, out.tolist()))
 

@@ -36,7 +36,9 @@
  *       compiled with -fno-builtin-sin -fno-builtin-cos -fno-builtin-sincos:
  *       gcc otherwise merges a sin and a cos of one argument into a sincos
  *       call, whose result can differ in the last bit where the exact value
- *       lies almost half-way between two doubles.
+ *       lies almost half-way between two doubles;
+ *   R9  entropy -int f log f over the points where f > 0 (the spline can
+ *       make f slightly negative; that mass is reported on its own).
  */
 #include <math.h>
 #include <stdint.h>
@@ -217,9 +219,12 @@ static double sum64_total(sum64 *s)
 /* Column sums over the momentum rows, R6 refined for the 2D sum: rows are
  * taken in blocks of 16 consecutive rows, each block summed serially from 0,
  * and the block sums are combined by sum64 over the block index.  The term of
- * row j is w_j * f (fused) when a weight row is given, f*f when square != 0,
- * else f. */
-static double column_sum(const oracle_params *P, const double *f, int64_t i, const double *w, int square)
+ * row j is w_j * f (fused) when a weight row is given, else by `term`:
+ * TERM_F f, TERM_SQUARE f*f (fused), TERM_FLOGF f*log(f) for f > 0 and 0
+ * otherwise (entropy density, R9), TERM_NEG f for f < 0 and 0 otherwise. */
+enum { TERM_F = 0, TERM_SQUARE = 1, TERM_FLOGF = 2, TERM_NEG = 3 };
+
+static double column_sum(const oracle_params *P, const double *f, int64_t i, const double *w, int term)
 {
     sum64 s;
     sum64_init(&s);
@@ -230,8 +235,12 @@ static double column_sum(const oracle_params *P, const double *f, int64_t i, con
             double v = f[j * P->nx + i];
             if (w)
                 blk = fma(w[j], v, blk);
-            else if (square)
+            else if (term == TERM_SQUARE)
                 blk = fma(v, v, blk);
+            else if (term == TERM_FLOGF)
+                blk = blk + (v > 0.0 ? v * log(v) : 0.0);
+            else if (term == TERM_NEG)
+                blk = blk + (v < 0.0 ? v : 0.0);
             else
                 blk = blk + v;
         }
@@ -244,7 +253,7 @@ static double column_sum(const oracle_params *P, const double *f, int64_t i, con
 void oracle_density(const oracle_params *P, const double *f, double *rho)
 {
     double dp = grid_dp(P);
-    for (int64_t i = 0; i < P->nx; i++) rho[i] = dp * column_sum(P, f, i, NULL, 0);
+    for (int64_t i = 0; i < P->nx; i++) rho[i] = dp * column_sum(P, f, i, NULL, TERM_F);
 }
 
 /* Magnetization, eq. (mxmydef): M_x = int cos(theta) rho, M_y = int sin(theta) rho. */
@@ -422,7 +431,8 @@ void oracle_sweep_p(const oracle_params *P, const double *f, double *out, const 
 
 /* Diagnostics of the current f (the quantities of the accuracy study of
  * Sec. 4.1): out = {mass, momentum, kinetic, potential, energy, M_x, M_y,
- * sum f^2 dx dp}.  Potential energies with unit-mass normalisation (R7):
+ * sum f^2 dx dp, entropy (R9; eq. casimirs with s(f) = -f log f),
+ * negative mass dx dp sum_{f<0} f}.  Potential energies with unit-mass normalisation (R7):
  *   HMF   W = (mass^2 - M_x^2 - M_y^2)/2            (eqs. hmfpot, mxmydef)
  *   ring  W = 1/2 dx^2 sum_i sum_k V(x_i-x_k) rho_i rho_k, self term included
  *   sheet W = pi G dx^2 sum_i sum_k |x_i-x_k| rho_i rho_k
@@ -438,22 +448,28 @@ void oracle_moments(const oracle_params *P, const double *f, double *out)
         pw[j] = node_p(P, j);
         kw[j] = 0.5 * (pw[j] * pw[j]);
     }
-    sum64 sm, sj, sk, sq;
+    sum64 sm, sj, sk, sq, se, sn;
     sum64_init(&sm);
     sum64_init(&sj);
     sum64_init(&sk);
     sum64_init(&sq);
+    sum64_init(&se);
+    sum64_init(&sn);
     for (int64_t i = 0; i < nx; i++) {
-        rho[i] = dp * column_sum(P, f, i, NULL, 0);
+        rho[i] = dp * column_sum(P, f, i, NULL, TERM_F);
         sum64_add(&sm, i, rho[i]);
-        sum64_add(&sj, i, dp * column_sum(P, f, i, pw, 0));
-        sum64_add(&sk, i, dp * column_sum(P, f, i, kw, 0));
-        sum64_add(&sq, i, dp * column_sum(P, f, i, NULL, 1));
+        sum64_add(&sj, i, dp * column_sum(P, f, i, pw, TERM_F));
+        sum64_add(&sk, i, dp * column_sum(P, f, i, kw, TERM_F));
+        sum64_add(&sq, i, dp * column_sum(P, f, i, NULL, TERM_SQUARE));
+        sum64_add(&se, i, dp * column_sum(P, f, i, NULL, TERM_FLOGF));
+        sum64_add(&sn, i, dp * column_sum(P, f, i, NULL, TERM_NEG));
     }
     double mass = dx * sum64_total(&sm);
     double mom = dx * sum64_total(&sj);
     double kin = dx * sum64_total(&sk);
     double l2 = dx * sum64_total(&sq);
+    double entropy = -(dx * sum64_total(&se));
+    double negmass = dx * sum64_total(&sn);
     double mx = 0.0, my = 0.0, W = 0.0;
     if (P->model == MODEL_HMF || P->model == MODEL_RING) magnetization(P, rho, &mx, &my);
     if (P->model == MODEL_HMF) {
@@ -483,6 +499,8 @@ void oracle_moments(const oracle_params *P, const double *f, double *out)
     out[5] = mx;
     out[6] = my;
     out[7] = l2;
+    out[8] = entropy;
+    out[9] = negmass;
     free(pw);
     free(kw);
     free(rho);

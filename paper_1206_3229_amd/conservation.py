@@ -1,0 +1,88 @@
+"""Conservation study of Sec. 4.1 (Tables 1-2): the largest relative change of
+the energy (delta e) and of the total norm (delta Norm, the mass) over a run
+of the self-gravitating sheets, and the entropy -int f log f over time.
+
+Setup of the paper's tables: x and p in [-2, 2], n_x = n_p = 256 ... 2048,
+waterbag x0 = 1, p0 = 0.5 (no noise), dt = 0.01 and 0.1, and the pair
+potential of eq. (sheetpot), V = |x|, i.e. G = 1/(2 pi) in this solver's
+2 pi G |x| (the 4096^2 sheet workload uses G = 1).  The paper does not
+state the end time of the table runs; it is a parameter here (default
+t = 100).  Boundaries follow the sheet readings of this solver: f = 0 outside
+the x box, periodic in p.  The moments are sampled every `every` steps (the
+run is split into calls of that many steps, which changes no result).
+
+    python -m paper_1206_3229_amd.conservation [--t-end 100] [--sizes 256,512]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+from . import inputs as I
+
+
+def sheet_table_params(n: int, dt: float, storage: int = I.STORAGE_F64) -> I.Params:
+    return I.Params(I.MODEL_SHEET, n, n, -2.0, 2.0, -2.0, 2.0, dt, bc_x=I.BC_ZERO, storage=storage,
+                    sheet_G=1.0 / (2.0 * math.pi))
+
+
+def track(V, params, f0, nsteps: int, every: int) -> dict:
+    """Run nsteps, sampling the moments every `every` steps."""
+    s = V.Solver(params, f0)
+    m0 = s.moments()
+    e_max = n_max = 0.0
+    ent = [(0, m0["entropy"])]
+    done = 0
+    t0 = time.perf_counter()
+    while done < nsteps:
+        k = min(every, nsteps - done)
+        s.step(k)
+        done += k
+        m = s.moments()
+        e_max = max(e_max, abs(m["energy"] - m0["energy"]) / abs(m0["energy"]))
+        n_max = max(n_max, abs(m["mass"] - m0["mass"]) / abs(m0["mass"]))
+        ent.append((done, m["entropy"]))
+    secs = time.perf_counter() - t0
+    last = s.moments()
+    s.close()
+    return {"delta_e": e_max, "delta_norm": n_max, "entropy_start": ent[0][1], "entropy_end": ent[-1][1],
+            "neg_mass_end": last["neg_mass"], "steps": nsteps, "samples": len(ent) - 1, "seconds": secs}
+
+
+def paper_tables(V, sizes=(256, 512, 1024, 2048), dts=(0.01, 0.1), t_end: float = 100.0,
+                 samples: int = 100, storage: int = I.STORAGE_F64) -> list[dict]:
+    rows = []
+    for dt in dts:
+        nsteps = int(round(t_end / dt))
+        every = max(1, nsteps // samples)
+        for n in sizes:
+            p = sheet_table_params(n, dt, storage)
+            f0 = I.waterbag(p, 1.0, 0.5)
+            r = track(V, p, f0, nsteps, every)
+            rows.append({"n": n, "dt": dt, "t_end": t_end, **r})
+    return rows
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--t-end", type=float, default=100.0)
+    ap.add_argument("--sizes", default="256,512,1024,2048")
+    ap.add_argument("--dts", default="0.01,0.1")
+    ap.add_argument("--samples", type=int, default=100)
+    ap.add_argument("--storage", type=int, default=0)
+    args = ap.parse_args()
+    import torch
+    from . import vlasov as V
+    if not torch.cuda.is_available():
+        raise SystemExit("conservation: no GPU visible")
+    V.load()
+    rows = paper_tables(V, tuple(int(v) for v in args.sizes.split(",")), tuple(float(v) for v in args.dts.split(",")),
+                        args.t_end, args.samples, args.storage)
+    for r in rows:
+        print(json.dumps(r), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -50,8 +50,8 @@ Layout layout_of(const vlasov_params &p)
     L.mxmy = take(2 * sizeof(double));
     L.hist = take((size_t)p.hist_cap * 2 * sizeof(double));
     L.hcount = take(sizeof(int64_t));
-    L.mom_out = take(8 * sizeof(double));
-    L.mom_col = take(4 * nx * sizeof(double));
+    L.mom_out = take(10 * sizeof(double));
+    L.mom_col = take(6 * nx * sizeof(double));
     L.mom_phi = take(nx * sizeof(double));
     L.total = o;
     return L;
@@ -597,7 +597,16 @@ int vlasov_moments(vlasov_ctx *c, vlasov_moments_t *out)
         launch(c, VLASOV_K_MOMENTS, vk::k_mom_blocks<double>, grid, dim3(256), (const double *)c->fcur(), scratch, nx,
                (int)P.np, (int)c->nblk, P.pmin, c->dp);
     launch(c, VLASOV_K_MOMENTS, vk::k_mom_cols, dim3((unsigned)((nx + 3) / 4)), dim3(256), scratch, col, nx,
-           (int)c->nblk, c->dp);
+           (int)c->nblk, c->dp, 4, 0);
+    // entropy density and negative mass: a second block pass over the scratch
+    if (P.storage == VLASOV_F32)
+        launch(c, VLASOV_K_MOMENTS, vk::k_mom_blocks2<float>, grid, dim3(256), (const float *)c->fcur(), scratch, nx,
+               (int)P.np, (int)c->nblk);
+    else
+        launch(c, VLASOV_K_MOMENTS, vk::k_mom_blocks2<double>, grid, dim3(256), (const double *)c->fcur(), scratch,
+               nx, (int)P.np, (int)c->nblk);
+    launch(c, VLASOV_K_MOMENTS, vk::k_mom_cols, dim3((unsigned)((nx + 3) / 4)), dim3(256), scratch, col, nx,
+           (int)c->nblk, c->dp, 2, 4);
     double wcoef = 0.0;
     if (P.model == VLASOV_MODEL_RING) {
         launch(c, VLASOV_K_MOMENTS, vk::k_mom_phi<true>, dim3((unsigned)((nx + 3) / 4)), dim3(256), col,
@@ -612,7 +621,7 @@ int vlasov_moments(vlasov_ctx *c, vlasov_moments_t *out)
            c->at<double>(c->L.sn), res, nx, c->dx, (int)P.model, wcoef);
     int rc = check_launch("moments");
     if (rc) return rc;
-    double h[8];
+    double h[10];
     HIP_TRY(hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     out->mass = h[0];
@@ -623,6 +632,8 @@ int vlasov_moments(vlasov_ctx *c, vlasov_moments_t *out)
     out->mx = h[5];
     out->my = h[6];
     out->l2 = h[7];
+    out->entropy = h[8];
+    out->neg_mass = h[9];
     for (double v : h)
         if (!isfinite(v)) return fail(VLASOV_E_NONFINITE, "non-finite diagnostic");
     return VLASOV_OK;

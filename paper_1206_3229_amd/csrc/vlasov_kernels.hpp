@@ -969,20 +969,43 @@ static __global__ __launch_bounds__(256) void k_mom_blocks(const T *__restrict__
     scratch[3 * plane + o] = s3;
 }
 
-// Pass 2: column quantities col[q][i] = dp * sum over blocks (one wavefront
-// per column).
+// Pass 1b: 16-row block sums of f log f over f > 0 (entropy density) and of
+// f over f < 0 (negative mass), into planes 0 and 1 of the scratch.
+template <typename T>
+static __global__ __launch_bounds__(256) void k_mom_blocks2(const T *__restrict__ f, double *__restrict__ scratch,
+                                                     int nx, int np, int nblk)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= nx) return;
+    const int b = blockIdx.y;
+    const int j0 = b * ROWS_PER_BLOCK;
+    const int jend = min(j0 + ROWS_PER_BLOCK, np);
+    double se = 0.0, sn = 0.0;
+    for (int j = j0; j < jend; ++j) {
+        const double v = (double)f[(size_t)j * nx + i];
+        se = se + (v > 0.0 ? v * log(v) : 0.0);
+        sn = sn + (v < 0.0 ? v : 0.0);
+    }
+    const size_t plane = (size_t)nblk * nx;
+    const size_t o = (size_t)b * nx + i;
+    scratch[o] = se;
+    scratch[plane + o] = sn;
+}
+
+// Pass 2: column quantities col[q0 + q][i] = dp * sum over blocks of scratch
+// plane q < nq (one wavefront per column).
 static __global__ __launch_bounds__(256) void k_mom_cols(const double *__restrict__ scratch, double *__restrict__ col,
-                                                  int nx, int nblk, double dp)
+                                                  int nx, int nblk, double dp, int nq, int q0)
 {
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= nx) return;
     const size_t plane = (size_t)nblk * nx;
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < nq; ++q) {
         double acc = 0.0;
         for (int b = lane; b < nblk; b += 64) acc = acc + scratch[q * plane + (size_t)b * nx + i];
         acc = wave_sum(acc);
-        if (lane == 0) col[(size_t)q * nx + i] = dp * acc;
+        if (lane == 0) col[(size_t)(q0 + q) * nx + i] = dp * acc;
     }
 }
 
@@ -1012,15 +1035,16 @@ static __global__ __launch_bounds__(256) void k_mom_phi(const double *__restrict
 }
 
 // Pass 4: totals (one wavefront).  out = {mass, momentum, kinetic, potential,
-// energy, mx, my, l2}.
+// energy, mx, my, l2, entropy, negative mass}.
 static __global__ __launch_bounds__(64) void k_mom_final(const double *__restrict__ col, const double *__restrict__ phi,
                                                   const double *__restrict__ cs, const double *__restrict__ sn,
                                                   double *__restrict__ out, int n, double dx, int model,
                                                   double wcoef)
 {
     const int lane = threadIdx.x;
-    const double *rho = col, *jj = col + n, *kk = col + 2 * n, *qq = col + 3 * n;
-    double sm = 0.0, sj = 0.0, sk = 0.0, sq = 0.0, c = 0.0, s = 0.0, w = 0.0;
+    const double *rho = col, *jj = col + n, *kk = col + 2 * n, *qq = col + 3 * n, *ee = col + 4 * n,
+                 *nn = col + 5 * n;
+    double sm = 0.0, sj = 0.0, sk = 0.0, sq = 0.0, se = 0.0, sneg = 0.0, c = 0.0, s = 0.0, w = 0.0;
     const bool angular = (model == 0 || model == 1);
     const bool pair = (model == 1 || model == 2);
     for (int i = lane; i < n; i += 64) {
@@ -1028,6 +1052,8 @@ static __global__ __launch_bounds__(64) void k_mom_final(const double *__restric
         sj = sj + jj[i];
         sk = sk + kk[i];
         sq = sq + qq[i];
+        se = se + ee[i];
+        sneg = sneg + nn[i];
         if (angular) {
             c = fma(cs[i], rho[i], c);
             s = fma(sn[i], rho[i], s);
@@ -1038,6 +1064,8 @@ static __global__ __launch_bounds__(64) void k_mom_final(const double *__restric
     sj = wave_sum(sj);
     sk = wave_sum(sk);
     sq = wave_sum(sq);
+    se = wave_sum(se);
+    sneg = wave_sum(sneg);
     c = wave_sum(c);
     s = wave_sum(s);
     w = wave_sum(w);
@@ -1060,6 +1088,8 @@ static __global__ __launch_bounds__(64) void k_mom_final(const double *__restric
         out[5] = mx;
         out[6] = my;
         out[7] = dx * sq;
+        out[8] = -(dx * se);
+        out[9] = dx * sneg;
     }
 }
 

@@ -37,7 +37,8 @@ class Params(C.Structure):
 
 
 class Moments(C.Structure):
-    _fields_ = [(n, C.c_double) for n in ("mass", "momentum", "kinetic", "potential", "energy", "mx", "my", "l2")]
+    _fields_ = [(n, C.c_double) for n in ("mass", "momentum", "kinetic", "potential", "energy", "mx", "my", "l2",
+                                          "entropy", "neg_mass")]
 
     def as_dict(self) -> dict:
         return {n: getattr(self, n) for n, _ in self._fields_}

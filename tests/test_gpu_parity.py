@@ -39,6 +39,17 @@ def assert_same(got, want, what=""):
     assert np.array_equal(got, want, equal_nan=True), f"{what}: not bitwise (max|d| = {err:.3e})"
 
 
+def assert_moments(got, want, what=""):
+    """Every diagnostic bit for bit, except the entropy, whose log is the
+    device's on one side and the C library's on the other (relative 1e-12)."""
+    assert set(got) == set(want)
+    for k in want:
+        if k == "entropy":
+            assert abs(got[k] - want[k]) <= 1e-12 * max(1.0, abs(want[k])), (what, k, got[k], want[k])
+        else:
+            assert got[k] == want[k], (what, k, got[k], want[k])
+
+
 def hmf(nx, np_, dt=0.1, storage=0, pmax=2.5):
     return I.Params(I.MODEL_HMF, nx, np_, -math.pi, math.pi, -pmax, pmax, dt, storage=storage)
 
@@ -123,8 +134,7 @@ def test_hmf_small_waterbag_full_run(V, oracle):
     want, hist_want = oracle.run(p, f0, nsteps, history=True)
     assert_same(got, want, "f after 100 steps")
     assert np.array_equal(hist, hist_want)
-    mom_want = oracle.moments(p, want)
-    assert mom == mom_want
+    assert_moments(mom, oracle.moments(p, want), "hmf small")
 
 
 @pytest.mark.parametrize("name", ["ring96x64", "sheet200x72", "hmf_f32", "ring_f32", "sheet_f32", "hmf_gauss"])
@@ -142,7 +152,7 @@ def test_models_short_runs(V, oracle, name):
     assert_same(got, want, name)
     if p.model in (I.MODEL_HMF, I.MODEL_RING):
         assert np.array_equal(hist, hist_want)
-    assert mom == oracle.moments(p, want)
+    assert_moments(mom, oracle.moments(p, want), name)
 
 
 def test_external_whole_cell_step_is_roll(V):
@@ -267,3 +277,20 @@ def test_full_size_matches_oracle(V, oracle, name):
     assert_same(got, want, name)
     if p.model in (I.MODEL_HMF, I.MODEL_RING):
         assert np.array_equal(hist, hist_want)
+
+
+def test_entropy_and_negative_mass_of_an_overshooting_state(V, oracle):
+    # a step in f: the spline overshoots below zero after a few steps
+    p = I.Params(I.MODEL_SHEET, 160, 96, -4.0, 4.0, -3.0, 3.0, 0.13, bc_x=I.BC_ZERO)
+    f0 = I.waterbag(p, 1.0, 0.7, 1e-4, 2)
+    for storage in (0, 1):
+        q = I.Params(**{**p.as_dict(), "storage": storage})
+        _log(f"entropy/negative mass storage={storage}")
+        s = V.Solver(q, f0)
+        s.step(9)
+        got, mom = s.read_f(), s.moments()
+        s.close()
+        want = oracle.run(q, f0, 9)
+        assert np.array_equal(got, want)
+        assert (want < 0).any() and mom["neg_mass"] < 0
+        assert_moments(mom, oracle.moments(q, want), f"overshoot storage={storage}")

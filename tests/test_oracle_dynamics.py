@@ -169,3 +169,22 @@ def test_fp32_storage_stays_close(oracle):
     assert np.all(f32 == f32.astype(np.float32).astype(np.float64))
     err = np.max(np.abs(f32 - f64)) / np.max(np.abs(f64))
     assert 1e-9 < err < 1e-5
+
+
+def test_sheet_energy_error_matches_table_2(oracle):
+    # Table 2 (dt = 0.1), n = 256: delta e = 5e-4 printed with one digit.
+    # Reading: end time t = 100 (not stated), energy sampled every 10 steps,
+    # f = 0 outside the x box, periodic p, V = |x| (G = 1/(2 pi) here).
+    import json
+    import os
+    from paper_1206_3229_amd import conservation as Cn
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sheet_tables.json")))
+    printed = golden["fd"]["0.1"]["256"][0]
+    p = Cn.sheet_table_params(256, 0.1)
+    f = I.waterbag(p, 1.0, 0.5)
+    e0 = oracle.moments(p, f)["energy"]
+    de = 0.0
+    for _ in range(100):
+        f = oracle.run(p, f, 10)
+        de = max(de, abs(oracle.moments(p, f)["energy"] - e0) / abs(e0))
+    assert 0.9 * printed <= de < 1.1 * printed, de  # rounds to the printed digit

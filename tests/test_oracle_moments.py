@@ -84,3 +84,44 @@ def test_fp32_cubic_within_single_precision(oracle):
             x = i - shift - 30
             want = 0.3 - 0.02 * x + 0.004 * x ** 2 - 1e-4 * x ** 3
             assert abs(got[i] - want) < 2e-5, (shift, i)
+
+
+# ---------------------------------------------------------------------------
+# Entropy -int f log f (eq. casimirs with s(f) = -f log f) over f > 0, and the
+# negative mass the spline's overshoot can create.
+# ---------------------------------------------------------------------------
+
+def test_entropy_of_a_waterbag_is_minus_log_of_its_level(oracle):
+    # f = c on K cells with c K dx dp = 1: S = -K dx dp c log c = -log c
+    p, f0, _ = I.hmf_waterbag_small()
+    f = (f0 > 0).astype(np.float64)
+    f /= p.dx * p.dp * f.sum()
+    c = float(f.max())
+    m = oracle.moments(p, f)
+    assert abs(m["entropy"] - (-math.log(c))) <= 1e-13 * abs(math.log(c))
+    assert m["neg_mass"] == 0.0
+
+
+def test_entropy_and_negative_mass_are_the_direct_sums(oracle):
+    p = I.Params(I.MODEL_SHEET, 70, 45, -3.0, 3.0, -2.0, 2.0, 0.1, bc_x=I.BC_ZERO)
+    f = np.random.default_rng(9).normal(0.2, 0.3, (p.np_, p.nx))  # about a quarter negative
+    pos = f[f > 0]
+    m = oracle.moments(p, f)
+    cell = p.dx * p.dp
+    want_s = -cell * fsum(pos * np.log(pos))
+    want_n = cell * fsum(f[f < 0])
+    assert (f < 0).sum() > 500
+    assert abs(m["entropy"] - want_s) <= 1e-14 * cell * fsum(np.abs(pos * np.log(pos)))
+    assert abs(m["neg_mass"] - want_n) <= 1e-14 * cell * fsum(np.abs(f[f < 0]))
+
+
+def test_entropy_of_a_maxwellian_is_the_continuous_value(oracle):
+    # f = exp(-p^2/2T) / (L sqrt(2 pi T)) uniform in x over a box of length L:
+    # S = log L + log(2 pi T)/2 + 1/2 (the grid sum converges spectrally)
+    T, L = 0.5, 2 * math.pi
+    p = I.Params(I.MODEL_HMF, 32, 256, -math.pi, math.pi, -8.0, 8.0, 0.1)
+    v = I.nodes(p.np_, p.pmin, p.pmax)
+    f = np.repeat((np.exp(-v * v / (2 * T)) / (L * math.sqrt(2 * math.pi * T)))[:, None], p.nx, axis=1)
+    m = oracle.moments(p, f)
+    assert abs(m["entropy"] - (math.log(L) + 0.5 * math.log(2 * math.pi * T) + 0.5)) < 1e-12
+    assert abs(m["mass"] - 1.0) < 1e-13
