@@ -32,7 +32,7 @@ def build(force: bool = True) -> str:
 
 class _P(C.Structure):
     _fields_ = [("model", C.c_int32), ("storage", C.c_int32), ("bc_x", C.c_int32), ("bc_p", C.c_int32),
-                ("nx", C.c_int64), ("np", C.c_int64),
+                ("spline", C.c_int32), ("reserved", C.c_int32), ("nx", C.c_int64), ("np", C.c_int64),
                 ("xmin", C.c_double), ("xmax", C.c_double), ("pmin", C.c_double), ("pmax", C.c_double),
                 ("dt", C.c_double), ("ring_eps", C.c_double), ("sheet_G", C.c_double)]
 
@@ -59,6 +59,7 @@ def _load():
         lib.oracle_second_difference.restype = C.c_double
         lib.oracle_foot.argtypes = [C.c_double, C.POINTER(C.c_int64), _D]
         lib.oracle_interpolate_line.argtypes = [_D, _D, C.c_int64, C.c_double, C.c_int, C.c_int]
+        lib.oracle_interpolate_line_gs.argtypes = [_D, _D, C.c_int64, C.c_double, C.c_int, C.c_int]
         lib.oracle_ring_dV.argtypes = [PP, C.c_int64]
         lib.oracle_ring_dV.restype = C.c_double
         lib.oracle_ring_V.argtypes = [PP, C.c_int64]
@@ -68,7 +69,8 @@ def _load():
 
 
 def _params(p) -> _P:
-    return _P(int(p.model), int(p.storage), int(p.bc_x), int(p.bc_p), int(p.nx), int(p.np_),
+    return _P(int(p.model), int(p.storage), int(p.bc_x), int(p.bc_p), int(getattr(p, "spline", 0)), 0,
+              int(p.nx), int(p.np_),
               float(p.xmin), float(p.xmax), float(p.pmin), float(p.pmax), float(p.dt),
               float(p.ring_eps), float(p.sheet_G))
 
@@ -164,6 +166,15 @@ def interpolate_line(line: np.ndarray, shift: float, bc: int = 0, storage: int =
     line = _f64(line)
     out = np.empty_like(line)
     lib.oracle_interpolate_line(_ptr(line), _ptr(out), line.size, float(shift), int(bc), int(storage))
+    return out
+
+
+def interpolate_line_gs(line: np.ndarray, shift: float, bc: int = 0, storage: int = 0) -> np.ndarray:
+    """One line moved by `shift` cells with the global spline (eq. tridiagsys)."""
+    lib = _load()
+    line = _f64(line)
+    out = np.empty_like(line)
+    lib.oracle_interpolate_line_gs(_ptr(line), _ptr(out), line.size, float(shift), int(bc), int(storage))
     return out
 
 

@@ -38,7 +38,11 @@
  *       call, whose result can differ in the last bit where the exact value
  *       lies almost half-way between two doubles;
  *   R9  entropy -int f log f over the points where f > 0 (the spline can
- *       make f slightly negative; that mass is reported on its own).
+ *       make f slightly negative; that mass is reported on its own);
+ *   R10 the global spline of eq. (tridiagsys) with the diagonal read as
+ *       2 f''_i/3 (the standard spline condition of the cited method; as
+ *       printed, f''_i/3, the periodic system is singular at the shortest
+ *       wave), periodic or continued by zeros like the samples (R3).
  */
 #include <math.h>
 #include <stdint.h>
@@ -49,8 +53,11 @@ enum { MODEL_HMF = 0, MODEL_RING = 1, MODEL_SHEET = 2, MODEL_EXTERNAL = 3 };
 enum { BC_PERIODIC = 0, BC_ZERO = 1 };
 enum { STORE_F64 = 0, STORE_F32 = 1 };
 
+enum { SPLINE_FD = 0, SPLINE_GS = 1 };
+
 typedef struct {
     int32_t model, storage, bc_x, bc_p;
+    int32_t spline, reserved; /* SPLINE_FD: f'' by eq. (findif); SPLINE_GS: by eq. (tridiagsys) */
     int64_t nx, np;
     double xmin, xmax, pmin, pmax, dt, ring_eps, sheet_G;
 } oracle_params;
@@ -170,6 +177,125 @@ static void interpolate_line(const double *in, double *out, int64_t n, int64_t s
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Eq. (tridiagsys): the global spline.  Continuity of the first derivative  */
+/* across the nodes gives, for D_i = f''_i du^2 (R1) and reading the printed */
+/* diagonal f''_i/3 as 2 f''_i/3 (R10), the tridiagonal system               */
+/*   D_{i-1} + 4 D_i + D_{i+1} = 6 (f_{i+1} - 2 f_i + f_{i-1}).              */
+/* Periodic lines: the cyclic system, solved by Thomas elimination with the  */
+/* Sherman-Morrison correction for the two corner entries.  Zero extension:  */
+/* the line continued by zeros on both sides (GS_PAD cells, beyond which D   */
+/* is below 0.27^GS_PAD of its size and set to 0), solved by Thomas.         */
+/* ------------------------------------------------------------------------ */
+#define GS_PAD 64
+
+/* Solves the (1, 4, 1) system with diagonal b[] (b[0] and b[n-1] may be
+ * modified by the caller) for right-hand side r[] into x[]; work w[n]. */
+static void thomas_141(const double *b, const double *r, double *x, double *w, int64_t n)
+{
+    double piv = b[0];
+    x[0] = r[0] / piv;
+    for (int64_t i = 1; i < n; i++) {
+        w[i] = 1.0 / piv;
+        piv = b[i] - w[i];
+        x[i] = (r[i] - x[i - 1]) / piv;
+    }
+    for (int64_t i = n - 2; i >= 0; i--) x[i] -= w[i + 1] * x[i + 1];
+}
+
+/* D of a line of n samples (spacing `stride`).  Periodic: D[0..n).  Zero
+ * extension: D[0..n + 2 GS_PAD), D[k + GS_PAD] for node k in [-GS_PAD, n + GS_PAD). */
+static void gs_second_derivatives(const double *line, int64_t n, int64_t stride, int bc, double *D)
+{
+    if (bc == BC_PERIODIC) {
+        double *b = malloc((size_t)n * sizeof(double)), *r = malloc((size_t)n * sizeof(double));
+        double *u = malloc((size_t)n * sizeof(double)), *z = malloc((size_t)n * sizeof(double));
+        double *w = malloc((size_t)n * sizeof(double));
+        for (int64_t i = 0; i < n; i++) {
+            const double fm = line[((i - 1 + n) % n) * stride], f0 = line[i * stride], fp = line[((i + 1) % n) * stride];
+            r[i] = 6.0 * ((fp - 2.0 * f0) + fm);
+            b[i] = 4.0;
+            u[i] = 0.0;
+        }
+        /* A = A' + u v^T with u = (g, 0, .., 0, 1), v = (1, 0, .., 0, 1/g), g = -4 */
+        const double g = -4.0;
+        b[0] -= g;
+        b[n - 1] -= 1.0 / g;
+        u[0] = g;
+        u[n - 1] = 1.0;
+        thomas_141(b, r, D, w, n);
+        thomas_141(b, u, z, w, n);
+        const double fac = (D[0] + D[n - 1] / g) / ((1.0 + z[0]) + z[n - 1] / g);
+        for (int64_t i = 0; i < n; i++) D[i] -= fac * z[i];
+        free(b);
+        free(r);
+        free(u);
+        free(z);
+        free(w);
+        return;
+    }
+    const int64_t N = n + 2 * GS_PAD;
+    double *b = malloc((size_t)N * sizeof(double)), *r = malloc((size_t)N * sizeof(double));
+    double *w = malloc((size_t)N * sizeof(double));
+    for (int64_t e = 0; e < N; e++) {
+        const int64_t i = e - GS_PAD;
+        const double fm = (i - 1 >= 0 && i - 1 < n) ? line[(i - 1) * stride] : 0.0;
+        const double f0 = (i >= 0 && i < n) ? line[i * stride] : 0.0;
+        const double fp = (i + 1 >= 0 && i + 1 < n) ? line[(i + 1) * stride] : 0.0;
+        r[e] = 6.0 * ((fp - 2.0 * f0) + fm);
+        b[e] = 4.0;
+    }
+    thomas_141(b, r, D, w, N);
+    free(b);
+    free(r);
+    free(w);
+}
+
+/* The backward semi-Lagrangian update of one line with the global spline:
+ * as interpolate_line, with D from eq. (tridiagsys).  FP32 storage: D is
+ * solved in FP64 from the stored samples and rounded, the combination runs
+ * in FP32. */
+static void interpolate_line_gs(const double *in, double *out, int64_t n, int64_t stride, double shift, int bc,
+                                int storage)
+{
+    foot_t w = foot_of_shift(shift);
+    double *D = malloc((size_t)(n + 2 * GS_PAD) * sizeof(double));
+    gs_second_derivatives(in, n, stride, bc, D);
+    for (int64_t i = 0; i < n; i++) {
+        int64_t k = i + w.m;
+        double Dk, Dk1;
+        if (bc == BC_PERIODIC) {
+            int64_t q = ((k % n) + n) % n, q1 = (((k + 1) % n) + n) % n;
+            Dk = D[q];
+            Dk1 = D[q1];
+        } else {
+            Dk = (k >= -GS_PAD && k < n + GS_PAD) ? D[k + GS_PAD] : 0.0;
+            Dk1 = (k + 1 >= -GS_PAD && k + 1 < n + GS_PAD) ? D[k + 1 + GS_PAD] : 0.0;
+        }
+        if (storage == STORE_F32) {
+            float r = (float)w.gamma * (float)Dk;
+            r = fmaf((float)w.delta, (float)Dk1, r);
+            r = fmaf((float)w.beta, samplef(in, n, stride, k + 1, bc), r);
+            out[i * stride] = (double)fmaf((float)w.alpha, samplef(in, n, stride, k, bc), r);
+        } else {
+            double r = w.gamma * Dk;
+            r = fma(w.delta, Dk1, r);
+            r = fma(w.beta, sample(in, n, stride, k + 1, bc), r);
+            out[i * stride] = fma(w.alpha, sample(in, n, stride, k, bc), r);
+        }
+    }
+    free(D);
+}
+
+static void interpolate(const oracle_params *P, const double *in, double *out, int64_t n, int64_t stride,
+                        double shift, int bc)
+{
+    if (P->spline == SPLINE_GS)
+        interpolate_line_gs(in, out, n, stride, shift, bc, P->storage);
+    else
+        interpolate_line(in, out, n, stride, shift, bc, P->storage);
+}
+
 static double grid_dx(const oracle_params *P) { return (P->xmax - P->xmin) / (double)P->nx; }
 static double grid_dp(const oracle_params *P) { return (P->pmax - P->pmin) / (double)P->np; }
 static double node_x(const oracle_params *P, int64_t i) { return P->xmin + (double)i * grid_dx(P); }
@@ -182,7 +308,7 @@ void oracle_advect_x(const oracle_params *P, const double *f, double *out, doubl
     double dx = grid_dx(P);
     for (int64_t j = 0; j < P->np; j++) {
         double shift = (node_p(P, j) * tau) / dx;
-        interpolate_line(f + j * P->nx, out + j * P->nx, P->nx, 1, shift, P->bc_x, P->storage);
+        interpolate(P, f + j * P->nx, out + j * P->nx, P->nx, 1, shift, P->bc_x);
     }
 }
 
@@ -193,7 +319,7 @@ void oracle_advect_p(const oracle_params *P, const double *f, double *out, const
     double dp = grid_dp(P);
     for (int64_t i = 0; i < P->nx; i++) {
         double shift = (F[i] * dt) / dp;
-        interpolate_line(f + i, out + i, P->np, P->nx, shift, P->bc_p, P->storage);
+        interpolate(P, f + i, out + i, P->np, P->nx, shift, P->bc_p);
     }
 }
 
@@ -525,6 +651,11 @@ void oracle_foot(double shift, int64_t *m, double *w4)
 void oracle_interpolate_line(const double *in, double *out, int64_t n, double shift, int bc, int storage)
 {
     interpolate_line(in, out, n, 1, shift, bc, storage);
+}
+
+void oracle_interpolate_line_gs(const double *in, double *out, int64_t n, double shift, int bc, int storage)
+{
+    interpolate_line_gs(in, out, n, 1, shift, bc, storage);
 }
 
 double oracle_ring_dV(const oracle_params *P, int64_t s) { return ring_dV_table(P, s); }

@@ -32,6 +32,7 @@ import numpy as np
 MODEL_HMF, MODEL_RING, MODEL_SHEET, MODEL_EXTERNAL = 0, 1, 2, 3
 BC_PERIODIC, BC_ZERO = 0, 1
 STORAGE_F64, STORAGE_F32 = 0, 1
+SPLINE_FD, SPLINE_GS = 0, 1  # f'' by eq. (findif) or by eq. (tridiagsys)
 
 _GOLDEN = np.uint64(0x9E3779B97F4A7C15)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
@@ -73,6 +74,7 @@ class Params:
     storage: int = STORAGE_F64
     ring_eps: float = 0.01
     sheet_G: float = 1.0
+    spline: int = SPLINE_FD
 
     @property
     def dx(self) -> float:
