@@ -68,6 +68,9 @@ typedef enum { VLASOV_F64 = 0, VLASOV_F32 = 1 } vlasov_storage;
  * grid reads 0; mass advected out of the box is lost). */
 typedef enum { VLASOV_BC_PERIODIC = 0, VLASOV_BC_ZERO = 1 } vlasov_bc;
 
+/* How f'' of the cubic spline of eq. (splinegen) is obtained. */
+typedef enum { VLASOV_SPLINE_FD = 0, VLASOV_SPLINE_GS = 1 } vlasov_spline;
+
 typedef struct {
     int32_t model;    /* vlasov_model */
     int32_t storage;  /* vlasov_storage */
@@ -79,6 +82,11 @@ typedef struct {
     double ring_eps;  /* softening of eq. (ringpot), > 0 (ring only) */
     double sheet_G;   /* coupling of the sheet model, F = 2 pi G (M(>x) - M(<x)) */
     int64_t hist_cap; /* entries kept of the per-step magnetization history (>= 0) */
+    int32_t spline;   /* VLASOV_SPLINE_FD: f'' by the local stencil of eq. (findif);
+                         VLASOV_SPLINE_GS: the global spline of eq. (tridiagsys), the
+                         paper's baseline (lines of at most 4096 samples, single contexts
+                         only: batches and the server reject it) */
+    int32_t reserved; /* 0 */
 } vlasov_params;
 
 /* Diagnostics of the current f (rectangle rule on the grid):

@@ -53,6 +53,7 @@ Layout layout_of(const vlasov_params &p)
     L.mom_out = take(10 * sizeof(double));
     L.mom_col = take(6 * nx * sizeof(double));
     L.mom_phi = take(nx * sizeof(double));
+    L.gs_g = take((vk::GS_K + 1) * sizeof(double));
     L.total = o;
     return L;
 }
@@ -74,6 +75,10 @@ std::string validate(const vlasov_params *p)
     if (p->model == VLASOV_MODEL_RING && !(isfinite(p->ring_eps) && p->ring_eps > 0.0)) return "ring_eps must be > 0";
     if (p->model == VLASOV_MODEL_SHEET && !isfinite(p->sheet_G)) return "sheet_G must be finite";
     if (p->hist_cap < 0) return "hist_cap must be >= 0";
+    if (p->spline != VLASOV_SPLINE_FD && p->spline != VLASOV_SPLINE_GS) return "unknown spline";
+    if (p->spline == VLASOV_SPLINE_GS && (p->nx > vk::GS_MAX_N || p->np > vk::GS_MAX_N))
+        return "the global spline takes lines of at most 4096 samples";
+    if (p->reserved != 0) return "reserved must be 0";
     return "";
 }
 
@@ -166,8 +171,16 @@ int launch_drift(vlasov_ctx *c, int npass, bool partials)
     }
 }
 
+int gs_drift(vlasov_ctx *c, bool partials);
+int gs_kick(vlasov_ctx *c);
+
 int drift(vlasov_ctx *c, int npass, bool partials)
 {
+    if (c->P.spline == VLASOV_SPLINE_GS) {  // two half drifts are two passes
+        int rc = VLASOV_OK;
+        for (int k = 0; k < npass && rc == VLASOV_OK; ++k) rc = gs_drift(c, partials && k + 1 == npass);
+        return rc;
+    }
     return c->P.storage == VLASOV_F32 ? launch_drift<float>(c, npass, partials)
                                       : launch_drift<double>(c, npass, partials);
 }
@@ -248,8 +261,70 @@ int launch_kick(vlasov_ctx *c)
 
 int kick(vlasov_ctx *c)
 {
+    if (c->P.spline == VLASOV_SPLINE_GS) return gs_kick(c);
     return c->P.storage == VLASOV_F32 ? launch_kick<float>(c) : launch_kick<double>(c);
 }
+
+// ---------------------------------------------------------------------------
+// Global spline (eq. tridiagsys): one workgroup per line; the kick runs on the
+// rows of the transpose.
+// ---------------------------------------------------------------------------
+template <typename T>
+int gs_drift_t(vlasov_ctx *c, bool partials)
+{
+    const vlasov_params &P = c->P;
+    const T *fin = (const T *)c->fcur();
+    T *fout = (T *)c->fnext();
+    const int32_t *dm = c->at<int32_t>(c->L.drift_m);
+    const double4 *dw = c->at<double4>(c->L.drift_w);
+    const double *g = c->at<double>(c->L.gs_g);
+    const double *nof = nullptr;
+    if (P.bc_x == VLASOV_BC_PERIODIC)
+        launch(c, VLASOV_K_DRIFT, vk::k_gs_line<T, vk::BC_PERIODIC, false>, dim3((unsigned)P.np), dim3(vk::GS_NT), fin,
+               fout, (int)P.nx, dm, dw, nof, 0.0, 0.0, g);
+    else
+        launch(c, VLASOV_K_DRIFT, vk::k_gs_line<T, vk::BC_ZERO, false>, dim3((unsigned)P.np), dim3(vk::GS_NT), fin,
+               fout, (int)P.nx, dm, dw, nof, 0.0, 0.0, g);
+    int rc = check_launch("global-spline drift");
+    if (rc) return rc;
+    c->cur ^= 1;
+    if (partials) {
+        launch(c, VLASOV_K_DRIFT, vk::k_partials<T>, dim3((unsigned)((P.nx + 255) / 256), (unsigned)c->nblk),
+               dim3(256), (const T *)c->fcur(), c->at<double>(c->L.part), (int)P.nx, (int)P.np);
+        rc = check_launch("partial sums");
+    }
+    return rc;
+}
+
+template <typename T>
+int gs_kick_t(vlasov_ctx *c)
+{
+    const vlasov_params &P = c->P;
+    const int nx = (int)P.nx, np = (int)P.np;
+    T *A = (T *)c->fcur(), *B = (T *)c->fnext();
+    const unsigned t1 = (unsigned)(((nx + 63) / 64) * ((np + 63) / 64));
+    launch(c, VLASOV_K_KICK, vk::k_transpose<T>, dim3(t1), dim3(256), (const T *)A, B, np, nx);  // B = A^T
+    const int32_t *nodm = nullptr;
+    const double4 *nodw = nullptr;
+    const double *g = c->at<double>(c->L.gs_g);
+    if (P.bc_p == VLASOV_BC_PERIODIC)
+        launch(c, VLASOV_K_KICK, vk::k_gs_line<T, vk::BC_PERIODIC, true>, dim3((unsigned)nx), dim3(vk::GS_NT),
+               (const T *)B, A, np, nodm, nodw, force_ptr(c), P.dt, c->dp, g);
+    else
+        launch(c, VLASOV_K_KICK, vk::k_gs_line<T, vk::BC_ZERO, true>, dim3((unsigned)nx), dim3(vk::GS_NT),
+               (const T *)B, A, np, nodm, nodw, force_ptr(c), P.dt, c->dp, g);
+    launch(c, VLASOV_K_KICK, vk::k_transpose<T>, dim3(t1), dim3(256), (const T *)A, B, nx, np);  // B = A^T
+    int rc = check_launch("global-spline kick");
+    if (rc == VLASOV_OK) c->cur ^= 1;
+    return rc;
+}
+
+int gs_drift(vlasov_ctx *c, bool partials)
+{
+    return c->P.storage == VLASOV_F32 ? gs_drift_t<float>(c, partials) : gs_drift_t<double>(c, partials);
+}
+
+int gs_kick(vlasov_ctx *c) { return c->P.storage == VLASOV_F32 ? gs_kick_t<float>(c) : gs_kick_t<double>(c); }
 
 // Fused kick and two half drifts (+ density partial sums) on tiles of TW
 // columns by RB density blocks.
@@ -304,7 +379,7 @@ int launch_kick_drift_w(vlasov_ctx *c)
 int kick_then_drift(vlasov_ctx *c, int npass, bool partials)
 {
     const int w = c->tune.kick_drift_width;
-    if (npass == 2 && partials && w != 0 && c->kd_ok) {
+    if (npass == 2 && partials && w != 0 && c->kd_ok && c->P.spline == VLASOV_SPLINE_FD) {
         const bool f32 = c->P.storage == VLASOV_F32;
         if (w == 256) return f32 ? launch_kick_drift_w<float, 256>(c) : launch_kick_drift_w<double, 256>(c);
         return f32 ? launch_kick_drift_w<float, 512>(c) : launch_kick_drift_w<double, 512>(c);
@@ -477,6 +552,17 @@ int vlasov_init(const vlasov_params *p, const double *f0_host, void *f_dev, void
             V[s] = Vd((double)e * c->dx);
         }
     }
+    // Green's function of the (1, 4, 1) operator of eq. (tridiagsys), times 6:
+    // g_k = sqrt(3) r^k, r = sqrt(3) - 2 (powers by repeated multiplication)
+    std::vector<double> gs(vk::GS_K + 1);
+    {
+        const double r = sqrt(3.0) - 2.0;
+        double gk = sqrt(3.0);
+        for (int k = 0; k <= vk::GS_K; ++k) {
+            gs[k] = gk;
+            gk *= r;
+        }
+    }
     const size_t nxb = (size_t)p->nx * sizeof(double);
     auto cleanup_fail = [&](int rc) {
         delete c;
@@ -494,7 +580,8 @@ int vlasov_init(const vlasov_params *p, const double *f0_host, void *f_dev, void
                {c->L.cs, cs.data(), nxb},
                {c->L.sn, sn.data(), nxb},
                {c->L.ringK, K.data(), nxb},
-               {c->L.ringV, V.data(), nxb}};
+               {c->L.ringV, V.data(), nxb},
+               {c->L.gs_g, gs.data(), gs.size() * sizeof(double)}};
     for (const auto &u : ups) {
         hipError_t e = hipMemcpyAsync(c->ws + u.off, u.src, u.bytes, hipMemcpyHostToDevice, c->stream);
         if (e != hipSuccess) return cleanup_fail(fail(VLASOV_E_HIP, std::string("table upload: ") + hipGetErrorString(e)));

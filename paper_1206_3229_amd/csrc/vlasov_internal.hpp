@@ -39,7 +39,7 @@ constexpr int KD_TW = 256, KD_RB = 1, KD_PF = 4;
 // Workspace layout (byte offsets, each 256-aligned).
 struct Layout {
     size_t drift_m, drift_w, kd_base, kd_rel, part, rho, F, Fext, cs, sn, ringK, ringV, mxmy, hist, hcount, mom_out,
-        mom_col, mom_phi;
+        mom_col, mom_phi, gs_g;
     size_t total;
 };
 

@@ -694,6 +694,146 @@ static __global__ __launch_bounds__(NT) void k_kick_drift(const T *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Eq. (tridiagsys): the global spline, the paper's baseline for the local f''.
+// D_i = f''_i du^2 solves D_{i-1} + 4 D_i + D_{i+1} = 6 S_i with S_i =
+// f_{i+1} - 2 f_i + f_{i-1} (on a periodic line, or on the line continued by
+// zeros).  Its solution is the convolution of 6 S with the Green's function of
+// the (1, 4, 1) operator, r^|k| / sqrt(12), r = sqrt(3) - 2: D_i = sum_k g_|k|
+// S_{i+k} with g_k = sqrt(3) r^k, truncated at |k| <= GS_K where |r|^GS_K is
+// below FP64 resolution.  On a periodic line the sum wraps around the line
+// (the periodic inverse is the wrapped infinite one).  One workgroup of 256
+// threads moves one line of n <= GS_MAX_N samples through LDS: the samples,
+// S and D (all with GS_E cells beyond each end), then the spline of eq.
+// (splinegen) at the feet.  Lines are the rows of f (the drift) or of its
+// transpose (the kick, shift from the force of the column).
+// ---------------------------------------------------------------------------
+constexpr int GS_K = 30, GS_E = GS_K + 2, GS_MAX_N = 4096, GS_NT = 256;
+constexpr int GS_LDS = GS_MAX_N + 2 * GS_E;
+
+template <typename T, int BC, bool KICK>
+static __global__ __launch_bounds__(GS_NT) void k_gs_line(const T *__restrict__ fin, T *__restrict__ fout, int n,
+                                                   const int32_t *__restrict__ dm,
+                                                   const double4 *__restrict__ dw,
+                                                   const double *__restrict__ F, double dt, double dh,
+                                                   const double *__restrict__ gtab)
+{
+    __shared__ T fe[GS_LDS], S[GS_LDS], D[GS_LDS];
+    __shared__ T g[GS_K + 1];
+    const int line = blockIdx.x, t = threadIdx.x;
+    const T *src = fin + (size_t)line * n;
+    const int ne = n + 2 * GS_E;  // extended index e = i + GS_E, i in [-GS_E, n + GS_E)
+    for (int k = t; k <= GS_K; k += GS_NT) g[k] = (T)gtab[k];
+    for (int e = t; e < ne; e += GS_NT) {
+        const int i = e - GS_E;
+        if (BC == BC_PERIODIC) {
+            // lines shorter than the extension wrap more than once
+            int q = i < 0 ? i + n : (i >= n ? i - n : i);
+            q = q < 0 ? wrap(q, n) : (q >= n ? wrap(q, n) : q);
+            fe[e] = src[q];
+        } else {
+            fe[e] = (i >= 0 && i < n) ? src[i] : T(0);
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < ne; e += GS_NT)
+        S[e] = (e == 0 || e == ne - 1) ? T(0) : (fe[e - 1] + fe[e + 1]) - T(2) * fe[e];
+    __syncthreads();
+    // D of the nodes of the line (periodic), or of every node of the
+    // extension [-GS_E + 1, n + GS_E - 1) (zero extension: D decays by |r|
+    // per cell away from the line, so farther feet read 0)
+    const int e0 = BC == BC_PERIODIC ? GS_E : 1, e1 = BC == BC_PERIODIC ? n + GS_E : ne - 1;
+    for (int e = e0 + t; e < e1; e += GS_NT) {
+        T acc;
+        if (BC == BC_PERIODIC) {
+            auto Sw = [&](int q) {  // periodic S of node q - GS_E
+                int i = q - GS_E;
+                i = i < 0 ? i + n : (i >= n ? i - n : i);
+                i = i < 0 ? wrap(i, n) : (i >= n ? wrap(i, n) : i);
+                return S[i + GS_E];
+            };
+            acc = g[GS_K] * (Sw(e - GS_K) + Sw(e + GS_K));
+            for (int k = GS_K - 1; k >= 1; --k) acc = vfma(g[k], Sw(e - k) + Sw(e + k), acc);
+            D[e] = vfma(g[0], Sw(e), acc);
+        } else {
+            auto Sz = [&](int q) { return (q >= 1 && q < ne - 1) ? S[q] : T(0); };
+            acc = g[GS_K] * (Sz(e - GS_K) + Sz(e + GS_K));
+            for (int k = GS_K - 1; k >= 1; --k) acc = vfma(g[k], Sz(e - k) + Sz(e + k), acc);
+            D[e] = vfma(g[0], Sz(e), acc);
+        }
+    }
+    __syncthreads();
+    // foot of the line's shift
+    int m;
+    T a, b, gg, d;
+    if (KICK) {
+        const Foot ft = foot_of_shift((F[line] * dt) / dh);
+        m = reduce_offset(ft.m, n, BC);
+        a = (T)ft.a;
+        b = (T)ft.b;
+        gg = (T)ft.g;
+        d = (T)ft.d;
+    } else {
+        m = dm[line];
+        const double4 w = dw[line];
+        a = (T)w.x;
+        b = (T)w.y;
+        gg = (T)w.z;
+        d = (T)w.w;
+    }
+    T *dst = fout + (size_t)line * n;
+    for (int i = t; i < n; i += GS_NT) {
+        const int k = i + m;  // cell [k, k + 1]
+        T fk, fk1, Dk, Dk1;
+        if (BC == BC_PERIODIC) {
+            const int q = k >= n ? k - n : k, q1 = q + 1 == n ? 0 : q + 1;  // m in [0, n)
+            fk = fe[q + GS_E];
+            fk1 = fe[q1 + GS_E];
+            Dk = D[q + GS_E];
+            Dk1 = D[q1 + GS_E];
+        } else {
+            fk = (k >= 0 && k < n) ? fe[k + GS_E] : T(0);
+            fk1 = (k + 1 >= 0 && k + 1 < n) ? fe[k + 1 + GS_E] : T(0);
+            Dk = (k > -GS_E && k < n + GS_E - 1) ? D[k + GS_E] : T(0);
+            Dk1 = (k + 1 > -GS_E && k + 1 < n + GS_E - 1) ? D[k + 1 + GS_E] : T(0);
+        }
+        dst[i] = spline(a, b, gg, d, fk, fk1, Dk, Dk1);
+    }
+}
+
+// Transpose of an rows x cols array through 64 x 64 LDS tiles (the kick of
+// the global spline runs on the rows of the transpose).
+template <typename T>
+static __global__ __launch_bounds__(256) void k_transpose(const T *__restrict__ in, T *__restrict__ out, int rows,
+                                                   int cols)
+{
+    __shared__ T tile[64][65];
+    const int tcols = (cols + 63) / 64;
+    const int bx = blockIdx.x % tcols, by = blockIdx.x / tcols;
+    const int c0 = bx * 64, r0 = by * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4)
+        if (r0 + r < rows && c0 + tx < cols) tile[r][tx] = in[(size_t)(r0 + r) * cols + c0 + tx];
+    __syncthreads();
+    for (int c = ty; c < 64; c += 4)
+        if (c0 + c < cols && r0 + tx < rows) out[(size_t)(c0 + c) * rows + r0 + tx] = tile[tx][c];
+}
+
+// Density partial sums of f (serial over the rows of each 16-row block, in
+// the order the drift kernels accumulate them).
+template <typename T>
+static __global__ __launch_bounds__(256) void k_partials(const T *__restrict__ f, double *__restrict__ part, int nx,
+                                                  int np)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= nx) return;
+    const int b = blockIdx.y;
+    const int jend = min(b * ROWS_PER_BLOCK + ROWS_PER_BLOCK, np);
+    double acc = 0.0;
+    for (int j = b * ROWS_PER_BLOCK; j < jend; ++j) acc = acc + (double)f[(size_t)j * nx + i];
+    part[(size_t)b * nx + i] = acc;
+}
+
+// ---------------------------------------------------------------------------
 // Density rho_i = dp * sum_j f_ji from the 16-row partial sums.  One
 // workgroup per 16 columns: thread (c, g) forms the serial sums of the block
 // classes l = g, g + 16, g + 32, g + 48 (blocks b = l mod 64, ascending b) of

@@ -33,7 +33,7 @@ class Params(C.Structure):
                 ("nx", C.c_int64), ("np", C.c_int64),
                 ("xmin", C.c_double), ("xmax", C.c_double), ("pmin", C.c_double), ("pmax", C.c_double),
                 ("dt", C.c_double), ("ring_eps", C.c_double), ("sheet_G", C.c_double),
-                ("hist_cap", C.c_int64)]
+                ("hist_cap", C.c_int64), ("spline", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Moments(C.Structure):
@@ -129,7 +129,7 @@ def to_params(p, hist_cap: int = 0) -> Params:
     """From paper_1206_3229_amd.inputs.Params."""
     return Params(int(p.model), int(p.storage), int(p.bc_x), int(p.bc_p), int(p.nx), int(p.np_),
                   float(p.xmin), float(p.xmax), float(p.pmin), float(p.pmax), float(p.dt),
-                  float(p.ring_eps), float(p.sheet_G), int(hist_cap))
+                  float(p.ring_eps), float(p.sheet_G), int(hist_cap), int(getattr(p, "spline", 0)), 0)
 
 
 def _dptr(a: np.ndarray):
