@@ -351,6 +351,21 @@ def main():
                                    "ms_per_step": secs32 / args.steps * 1e3,
                                    "kernels_us": {k: (v[0] / v[1] * 1e3 if v[1] else None)
                                                   for k, v in prof32.items()}}
+    if not args.no_extras:
+        # the paper's baseline interpolation (global spline, eq. tridiagsys) on the same workload
+        pg, fg, _ = WORKLOADS[args.workload]()
+        pg = I.Params(**{**pg.as_dict(), "spline": I.SPLINE_GS})
+        sg = V.Solver(pg, fg)
+        gsteps = max(1, args.steps // 10)
+        sg.step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sg.step(gsteps)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        sg.close()
+        out["global_spline"] = {"value": pg.nx * pg.np_ * gsteps / tg, "unit": "grid-point updates/s",
+                                "ms_per_step": tg / gsteps * 1e3, "steps": gsteps}
     if not args.no_copy:
         out["copy_ceiling_GBps"] = copy_ceiling(torch, V)
     if args.no_extras:

@@ -23,9 +23,9 @@ import time
 from . import inputs as I
 
 
-def sheet_table_params(n: int, dt: float, storage: int = I.STORAGE_F64) -> I.Params:
+def sheet_table_params(n: int, dt: float, storage: int = I.STORAGE_F64, spline: int = I.SPLINE_FD) -> I.Params:
     return I.Params(I.MODEL_SHEET, n, n, -2.0, 2.0, -2.0, 2.0, dt, bc_x=I.BC_ZERO, storage=storage,
-                    sheet_G=1.0 / (2.0 * math.pi))
+                    sheet_G=1.0 / (2.0 * math.pi), spline=spline)
 
 
 def track(V, params, f0, nsteps: int, every: int) -> dict:
@@ -52,16 +52,19 @@ def track(V, params, f0, nsteps: int, every: int) -> dict:
 
 
 def paper_tables(V, sizes=(256, 512, 1024, 2048), dts=(0.01, 0.1), t_end: float = 100.0,
-                 samples: int = 100, storage: int = I.STORAGE_F64) -> list[dict]:
+                 samples: int = 100, storage: int = I.STORAGE_F64, splines=(I.SPLINE_FD, I.SPLINE_GS)) -> list[dict]:
+    """Both columns of the tables: the local (FD) and the global (GS) spline."""
     rows = []
     for dt in dts:
         nsteps = int(round(t_end / dt))
         every = max(1, nsteps // samples)
         for n in sizes:
-            p = sheet_table_params(n, dt, storage)
-            f0 = I.waterbag(p, 1.0, 0.5)
-            r = track(V, p, f0, nsteps, every)
-            rows.append({"n": n, "dt": dt, "t_end": t_end, **r})
+            for spline in splines:
+                p = sheet_table_params(n, dt, storage, spline)
+                f0 = I.waterbag(p, 1.0, 0.5)
+                r = track(V, p, f0, nsteps, every)
+                rows.append({"n": n, "dt": dt, "spline": "gs" if spline == I.SPLINE_GS else "fd",
+                             "t_end": t_end, **r})
     return rows
 
 
