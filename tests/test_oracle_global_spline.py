@@ -61,3 +61,31 @@ def test_fp32_storage_within_single_precision(oracle):
     g64 = oracle.interpolate_line_gs(f.astype(np.float32).astype(np.float64), 2.37, I.BC_PERIODIC)
     g32 = oracle.interpolate_line_gs(f, 2.37, I.BC_PERIODIC, storage=I.STORAGE_F32)
     assert np.max(np.abs(g32 - g64)) < 2e-6
+
+
+def _gs_eigenvalue(kappa, theta):
+    # mode e^{i kappa l}: the system gives D = sigma f with
+    # (2 cos kappa + 4) sigma = 6 (2 cos kappa - 2)
+    sigma = -12.0 * math.sin(kappa / 2) ** 2 / (2.0 + math.cos(kappa))
+    a, b = 1 - theta, theta
+    g, d = (a ** 3 - a) / 6, (b ** 3 - b) / 6
+    return a + b * np.exp(1j * kappa) + sigma * (g + d * np.exp(1j * kappa))
+
+
+@pytest.mark.parametrize("q,shift", [(1, 0.3), (5, -2.6), (13, 7.45), (31, 0.5), (32, 0.5)])
+def test_fourier_modes_are_eigenvectors(oracle, q, shift):
+    n = 64
+    kappa = 2 * math.pi * q / n
+    l = np.arange(n)
+    got = oracle.interpolate_line_gs(np.cos(kappa * l + 0.4), shift, I.BC_PERIODIC)
+    m = math.floor(-shift)
+    lam = _gs_eigenvalue(kappa, -shift - m)
+    want = np.real(lam * np.exp(1j * (kappa * (l + m) + 0.4)))
+    assert np.max(np.abs(got - want)) < 5e-14
+
+
+def test_global_spline_never_amplifies():
+    worst = max(abs(_gs_eigenvalue(k, t)) for k in np.linspace(0, math.pi, 181) for t in np.linspace(0, 1, 101))
+    assert worst <= 1 + 1e-14
+    # the shortest wave half way between nodes is removed, as by the local spline
+    assert abs(_gs_eigenvalue(math.pi, 0.5)) < 1e-14
