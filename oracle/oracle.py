@@ -32,9 +32,11 @@ def build(force: bool = True) -> str:
 
 class _P(C.Structure):
     _fields_ = [("model", C.c_int32), ("storage", C.c_int32), ("bc_x", C.c_int32), ("bc_p", C.c_int32),
-                ("spline", C.c_int32), ("reserved", C.c_int32), ("nx", C.c_int64), ("np", C.c_int64),
+                ("spline", C.c_int32), ("splitting", C.c_int32), ("filter_every", C.c_int32), ("pad", C.c_int32),
+                ("nx", C.c_int64), ("np", C.c_int64),
                 ("xmin", C.c_double), ("xmax", C.c_double), ("pmin", C.c_double), ("pmax", C.c_double),
-                ("dt", C.c_double), ("ring_eps", C.c_double), ("sheet_G", C.c_double)]
+                ("dt", C.c_double), ("ring_eps", C.c_double), ("sheet_G", C.c_double),
+                ("filter_strength", C.c_double)]
 
 
 _lib = None
@@ -64,15 +66,19 @@ def _load():
         lib.oracle_ring_dV.restype = C.c_double
         lib.oracle_ring_V.argtypes = [PP, C.c_int64]
         lib.oracle_ring_V.restype = C.c_double
+        lib.oracle_filter_p.argtypes = [PP, _D, _D]
+        lib.oracle_split_weights.argtypes = [C.c_int, _D]
+        lib.oracle_split_weights.restype = C.c_int
         _lib = lib
     return _lib
 
 
 def _params(p) -> _P:
-    return _P(int(p.model), int(p.storage), int(p.bc_x), int(p.bc_p), int(getattr(p, "spline", 0)), 0,
+    return _P(int(p.model), int(p.storage), int(p.bc_x), int(p.bc_p), int(getattr(p, "spline", 0)),
+              int(getattr(p, "splitting", 0)), int(getattr(p, "filter_every", 0)), 0,
               int(p.nx), int(p.np_),
               float(p.xmin), float(p.xmax), float(p.pmin), float(p.pmax), float(p.dt),
-              float(p.ring_eps), float(p.sheet_G))
+              float(p.ring_eps), float(p.sheet_G), float(getattr(p, "filter_strength", 0.0)))
 
 
 def _ptr(a: np.ndarray):
@@ -84,19 +90,37 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
 
+def split_weights(scheme: int) -> list[float]:
+    """Sizes w_k (in units of dt) of the substeps of one step."""
+    w = np.zeros(8)
+    n = _load().oracle_split_weights(int(scheme), _ptr(w))
+    return [float(v) for v in w[:n]]
+
+
 def run(p, f0: np.ndarray, nsteps: int, F_ext=None, history: bool = False):
-    """nsteps time steps from f0; returns f (and the (nsteps, 2) magnetization
-    history of the drifted distributions if history=True)."""
+    """nsteps time steps from f0; returns f (and the magnetization history of
+    the drifted distributions, one (Mx, My) row per force evaluation, i.e.
+    nsteps times the number of substeps, if history=True)."""
     lib = _load()
     f = _f64(f0).copy()
     assert f.shape == (p.np_, p.nx)
-    hist = np.zeros((max(nsteps, 1), 2)) if history else None
+    nev = nsteps * len(split_weights(getattr(p, "splitting", 0)))
+    hist = np.zeros((max(nev, 1), 2)) if history else None
     fe = _f64(F_ext) if F_ext is not None else None
     rc = lib.oracle_run(C.byref(_params(p)), _ptr(f), int(nsteps), _ptr(fe) if fe is not None else None,
                         _ptr(hist) if hist is not None else None)
     if rc != 0:
         raise MemoryError("oracle_run failed")
-    return (f, hist[:nsteps]) if history else f
+    return (f, hist[:nev]) if history else f
+
+
+def filter_p(p, f: np.ndarray) -> np.ndarray:
+    """The filter along p (one application with p.filter_strength)."""
+    lib = _load()
+    f = _f64(f)
+    out = np.empty_like(f)
+    lib.oracle_filter_p(C.byref(_params(p)), _ptr(f), _ptr(out))
+    return out
 
 
 def sweep_x(p, f: np.ndarray, tau: float) -> np.ndarray:

@@ -42,7 +42,19 @@
  *   R10 the global spline of eq. (tridiagsys) with the diagonal read as
  *       2 f''_i/3 (the standard spline condition of the cited method; as
  *       printed, f''_i/3, the periodic system is singular at the shortest
- *       wave), periodic or continued by zeros like the samples (R3).
+ *       wave), periodic or continued by zeros like the samples (R3);
+ *   R11 higher-order time splitting (named in the conclusions as an
+ *       extension, after Arber and Vann): a step of size dt is the
+ *       composition of the Sec. 3 step (half drift, force, kick, half drift)
+ *       with sizes w_k dt; weights of the fourth-order symmetric compositions
+ *       of Yoshida / Forest-Ruth (w1, w0, w1) and Suzuki (p, p, 1-4p, p, p);
+ *       the drifts of consecutive substeps stay separate sweeps, as those of
+ *       consecutive steps do;
+ *   R12 filtering (the same passage): after the last kick of every k-th step,
+ *       f <- f - (sigma/256) delta_p^8 f along each column (delta_p^8 the
+ *       eighth central difference, binomial weights), which damps the mode
+ *       of wavenumber kappa by the factor 1 - sigma sin^8(kappa/2) and keeps
+ *       every p-moment of degree below 8 of each column.
  */
 #include <math.h>
 #include <stdint.h>
@@ -54,12 +66,17 @@ enum { BC_PERIODIC = 0, BC_ZERO = 1 };
 enum { STORE_F64 = 0, STORE_F32 = 1 };
 
 enum { SPLINE_FD = 0, SPLINE_GS = 1 };
+enum { SPLIT_STRANG = 0, SPLIT_TRIPLE_JUMP = 1, SPLIT_SUZUKI = 2 };
 
 typedef struct {
     int32_t model, storage, bc_x, bc_p;
-    int32_t spline, reserved; /* SPLINE_FD: f'' by eq. (findif); SPLINE_GS: by eq. (tridiagsys) */
+    int32_t spline;       /* SPLINE_FD: f'' by eq. (findif); SPLINE_GS: by eq. (tridiagsys) */
+    int32_t splitting;    /* R11 */
+    int32_t filter_every; /* R12: 0 = no filter */
+    int32_t pad;
     int64_t nx, np;
     double xmin, xmax, pmin, pmax, dt, ring_eps, sheet_G;
+    double filter_strength; /* R12: sigma */
 } oracle_params;
 
 /* ------------------------------------------------------------------------ */
@@ -499,6 +516,61 @@ void oracle_force(const oracle_params *P, const double *rho, const double *F_ext
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* R12: the filter along p.  For each column, with the samples of R3:        */
+/*   s_j = sum_m b_m f_{j+m},  b = (1, -8, 28, -56, 70, -56, 28, -8, 1),     */
+/* pairs added first and accumulated from the outermost pair inwards like    */
+/* the stencil of eq. (findif); out_j = f_j - (sigma/256) s_j as one fma.    */
+/* ------------------------------------------------------------------------ */
+void oracle_filter_p(const oracle_params *P, const double *f, double *out)
+{
+    const double c = P->filter_strength / 256.0;
+    for (int64_t i = 0; i < P->nx; i++) {
+        const double *col = f + i;
+        for (int64_t j = 0; j < P->np; j++) {
+            double v;
+            if (P->storage == STORE_F32) {
+                float s = samplef(col, P->np, P->nx, j - 4, P->bc_p) + samplef(col, P->np, P->nx, j + 4, P->bc_p);
+                s = fmaf(-8.0f, samplef(col, P->np, P->nx, j - 3, P->bc_p) + samplef(col, P->np, P->nx, j + 3, P->bc_p), s);
+                s = fmaf(28.0f, samplef(col, P->np, P->nx, j - 2, P->bc_p) + samplef(col, P->np, P->nx, j + 2, P->bc_p), s);
+                s = fmaf(-56.0f, samplef(col, P->np, P->nx, j - 1, P->bc_p) + samplef(col, P->np, P->nx, j + 1, P->bc_p), s);
+                const float fj = samplef(col, P->np, P->nx, j, P->bc_p);
+                s = fmaf(70.0f, fj, s);
+                v = (double)fmaf(-(float)c, s, fj);
+            } else {
+                double s = sample(col, P->np, P->nx, j - 4, P->bc_p) + sample(col, P->np, P->nx, j + 4, P->bc_p);
+                s = fma(-8.0, sample(col, P->np, P->nx, j - 3, P->bc_p) + sample(col, P->np, P->nx, j + 3, P->bc_p), s);
+                s = fma(28.0, sample(col, P->np, P->nx, j - 2, P->bc_p) + sample(col, P->np, P->nx, j + 2, P->bc_p), s);
+                s = fma(-56.0, sample(col, P->np, P->nx, j - 1, P->bc_p) + sample(col, P->np, P->nx, j + 1, P->bc_p), s);
+                const double fj = sample(col, P->np, P->nx, j, P->bc_p);
+                s = fma(70.0, fj, s);
+                v = fma(-c, s, fj);
+            }
+            out[j * P->nx + i] = v;
+        }
+    }
+}
+
+/* R11: weights w_k of the composition; returns their number.  The decimal
+ * constants are the doubles nearest to the exact values. */
+int oracle_split_weights(int scheme, double *w)
+{
+    switch (scheme) {
+    case SPLIT_TRIPLE_JUMP: /* w1 = 1/(2 - 2^(1/3)), w0 = -2^(1/3)/(2 - 2^(1/3)) */
+        w[0] = 1.3512071919596575;
+        w[1] = -1.7024143839193153;
+        w[2] = 1.3512071919596575;
+        return 3;
+    case SPLIT_SUZUKI: /* p = 1/(4 - 4^(1/3)) four times, 1 - 4p in the middle */
+        w[0] = w[1] = w[3] = w[4] = 0.4144907717943757;
+        w[2] = -0.657963087177503;
+        return 5;
+    default:
+        w[0] = 1.0;
+        return 1;
+    }
+}
+
 /* Storage rounding of the FP32 mode: f lives in FP32 between sweeps. */
 static void store_round(const oracle_params *P, double *f)
 {
@@ -507,23 +579,36 @@ static void store_round(const oracle_params *P, double *f)
     for (int64_t t = 0; t < N; t++) f[t] = (double)(float)f[t];
 }
 
-/* One time step, Sec. 3 steps 1-4: half drift, force from the drifted f, full
- * kick, half drift.  f is updated in place; `hist` (may be NULL) receives the
- * magnetization of the drifted f used by the force. */
-static int strang_step(const oracle_params *P, double *f, double *g, double *rho, double *F, const double *F_ext,
-                       double *hist)
+/* One time step: the Sec. 3 step (half drift, force from the drifted f, full
+ * kick, half drift) applied with the sizes w_k dt of R11 in turn (one
+ * substep of size dt for the paper's scheme), the filter of R12 after the
+ * last kick when `filtered`.  f is updated in place; `hist` (may be NULL)
+ * receives the magnetization of the drifted f of every force evaluation. */
+static int split_step(const oracle_params *P, double *f, double *g, double *rho, double *F, const double *F_ext,
+                      double *hist, int filtered)
 {
-    double tau = 0.5 * P->dt;
-    oracle_advect_x(P, f, g, tau);                   /* eq. (step1) */
-    oracle_density(P, g, rho);
-    oracle_force(P, rho, F_ext, F, hist);           /* eq. (step2) */
-    oracle_advect_p(P, g, f, F, P->dt);              /* eq. (step3) */
-    oracle_advect_x(P, f, g, tau);                   /* eq. (step4) */
-    memcpy(f, g, (size_t)(P->nx * P->np) * sizeof(double));
+    double w[8];
+    const int ns = oracle_split_weights(P->splitting, w);
+    for (int k = 0; k < ns; k++) {
+        const double h = w[k] * P->dt;
+        const double tau = 0.5 * h;
+        oracle_advect_x(P, f, g, tau);                         /* eq. (step1) */
+        oracle_density(P, g, rho);
+        oracle_force(P, rho, F_ext, F, hist ? hist + 2 * k : NULL); /* eq. (step2) */
+        oracle_advect_p(P, g, f, F, h);                        /* eq. (step3) */
+        if (filtered && k == ns - 1) {
+            oracle_filter_p(P, f, g);                          /* R12 */
+            memcpy(f, g, (size_t)(P->nx * P->np) * sizeof(double));
+        }
+        oracle_advect_x(P, f, g, tau);                         /* eq. (step4) */
+        memcpy(f, g, (size_t)(P->nx * P->np) * sizeof(double));
+    }
     return 0;
 }
 
-/* Run nsteps time steps in place.  hist (nullable) gets 2*nsteps values. */
+/* Run nsteps time steps in place.  hist (nullable) gets 2 values per force
+ * evaluation: 2 * nsteps * (number of substeps).  Step s (from 0) is filtered
+ * when filter_every > 0 and s + 1 is a multiple of it. */
 int oracle_run(const oracle_params *P, double *f, int64_t nsteps, const double *F_ext, double *hist)
 {
     int64_t N = P->nx * P->np;
@@ -536,8 +621,13 @@ int oracle_run(const oracle_params *P, double *f, int64_t nsteps, const double *
         free(F);
         return -2;
     }
+    double w[8];
+    const int ns = oracle_split_weights(P->splitting, w);
     store_round(P, f);
-    for (int64_t s = 0; s < nsteps; s++) strang_step(P, f, g, rho, F, F_ext, hist ? hist + 2 * s : NULL);
+    for (int64_t s = 0; s < nsteps; s++) {
+        const int filtered = P->filter_every > 0 && (s + 1) % P->filter_every == 0;
+        split_step(P, f, g, rho, F, F_ext, hist ? hist + 2 * ns * s : NULL, filtered);
+    }
     free(g);
     free(rho);
     free(F);

@@ -33,6 +33,7 @@ MODEL_HMF, MODEL_RING, MODEL_SHEET, MODEL_EXTERNAL = 0, 1, 2, 3
 BC_PERIODIC, BC_ZERO = 0, 1
 STORAGE_F64, STORAGE_F32 = 0, 1
 SPLINE_FD, SPLINE_GS = 0, 1  # f'' by eq. (findif) or by eq. (tridiagsys)
+SPLIT_STRANG, SPLIT_TRIPLE_JUMP, SPLIT_SUZUKI = 0, 1, 2  # time splitting: one step, or a 4th-order composition
 
 _GOLDEN = np.uint64(0x9E3779B97F4A7C15)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
@@ -75,6 +76,9 @@ class Params:
     ring_eps: float = 0.01
     sheet_G: float = 1.0
     spline: int = SPLINE_FD
+    splitting: int = SPLIT_STRANG
+    filter_every: int = 0
+    filter_strength: float = 0.0
 
     @property
     def dx(self) -> float:
