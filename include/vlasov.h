@@ -71,6 +71,19 @@ typedef enum { VLASOV_BC_PERIODIC = 0, VLASOV_BC_ZERO = 1 } vlasov_bc;
 /* How f'' of the cubic spline of eq. (splinegen) is obtained. */
 typedef enum { VLASOV_SPLINE_FD = 0, VLASOV_SPLINE_GS = 1 } vlasov_spline;
 
+/* Time splitting (the higher-order schemes the conclusions name as an
+ * extension).  A step of size dt applies the Sec. 3 step (half drift, force,
+ * kick, half drift) with the sizes w_k dt in turn:
+ *   STRANG      w = (1), the paper's scheme, second order;
+ *   TRIPLE_JUMP w = (w1, w0, w1), w1 = 1/(2 - 2^(1/3)), w0 = 1 - 2 w1
+ *               (Yoshida; Forest and Ruth), fourth order;
+ *   SUZUKI      w = (p, p, 1 - 4p, p, p), p = 1/(4 - 4^(1/3)), fourth order
+ *               with a smaller error constant.
+ * Each w_k is the double nearest to the exact value.  The drifts of
+ * consecutive substeps are separate sweeps (run fused in one kernel where
+ * possible, like those of consecutive steps). */
+typedef enum { VLASOV_SPLIT_STRANG = 0, VLASOV_SPLIT_TRIPLE_JUMP = 1, VLASOV_SPLIT_SUZUKI = 2 } vlasov_splitting;
+
 typedef struct {
     int32_t model;    /* vlasov_model */
     int32_t storage;  /* vlasov_storage */
@@ -86,7 +99,14 @@ typedef struct {
                          VLASOV_SPLINE_GS: the global spline of eq. (tridiagsys), the
                          paper's baseline (lines of at most 4096 samples, single contexts
                          only: batches and the server reject it) */
-    int32_t reserved; /* 0 */
+    int32_t splitting;    /* vlasov_splitting */
+    int32_t filter_every; /* 0: no filter; k > 0: after the last kick of every k-th step
+                             (counted from vlasov_init), f <- f - (sigma/256) d^8 f along
+                             each column, d^8 the eighth central difference in p (mode
+                             kappa damped by 1 - sigma sin^8(kappa/2); mass and every
+                             p-moment below degree 8 kept) */
+    int32_t reserved;     /* 0 */
+    double filter_strength; /* sigma, in (0, 1] when filter_every > 0 */
 } vlasov_params;
 
 /* Diagnostics of the current f (rectangle rule on the grid):
@@ -130,15 +150,17 @@ int vlasov_init(const vlasov_params *p, const double *f0_host, void *f_dev, void
  * VLASOV_E_STATE on other models. */
 int vlasov_set_external_force(vlasov_ctx *c, const double *F_host);
 
-/* Enqueue nsteps (>= 0) time steps of Sec. 3 (steps 1-4).  Consecutive half
- * drifts of successive steps are fused into one pass over f; the result is
- * bit-identical to nsteps separate steps. */
+/* Enqueue nsteps (>= 0) time steps of Sec. 3 (steps 1-4), each made of the
+ * substeps of params.splitting, and the filter of params.filter_every.
+ * Consecutive half drifts of successive (sub)steps are fused into one pass
+ * over f; the result is bit-identical to nsteps separate steps. */
 int vlasov_step(vlasov_ctx *c, int64_t nsteps);
 
-/* The individual sweeps of a step, for inspection and testing.
+/* The individual sweeps of a step, for inspection and testing (with the
+ * sizes of the first substep: dt itself for the Strang splitting).
  * vlasov_drift: npass (1 or 2) successive half drifts (eqs. step1/step4) of
- *   the current f, tau = dt/2 each; also leaves the density partial sums of
- *   the result.
+ *   the current f, tau = w_0 dt/2 each; also leaves the density partial sums
+ *   of the result.
  * vlasov_force: density of the current f and the model force (eq. step2);
  *   writes F (nx values) and the magnetization (2 values) to the host if the
  *   pointers are non-NULL (then synchronises), and keeps F for the kick.
@@ -152,15 +174,17 @@ int vlasov_kick(vlasov_ctx *c);
  * written) if any value is NaN or infinite. */
 int vlasov_moments(vlasov_ctx *c, vlasov_moments_t *out);
 
-/* Per-step magnetization (M_x, M_y) of the drifted f used by each force
- * evaluation (HMF and ring), oldest first.  Copies min(count, cap, hist_cap)
- * entries, sets *count to the number of steps recorded so far; synchronises. */
+/* Magnetization (M_x, M_y) of the drifted f used by each force evaluation
+ * (HMF and ring; one per substep), oldest first.  Copies min(count, cap,
+ * hist_cap) entries, sets *count to the number of evaluations recorded so
+ * far; synchronises. */
 int vlasov_mag_history(vlasov_ctx *c, double *mx, double *my, int64_t cap, int64_t *count);
 
 /* Copy the current f to the host as FP64 [np][nx]; synchronises. */
 int vlasov_read_f(vlasov_ctx *c, double *f_host);
 
-/* Replace the current f (checkpoint restore), FP64 [np][nx]; synchronises. */
+/* Replace the current f (checkpoint restore), FP64 [np][nx]; synchronises.
+ * The step count of the filter schedule is not changed. */
 int vlasov_write_f(vlasov_ctx *c, const double *f_host);
 
 /* Release the context (host memory only; caller device memory is untouched).
@@ -215,6 +239,7 @@ size_t vlasov_batch_scratch_bytes(int32_t chunk_cycles);
  * workgroups stride over the tiles of all grids; chunk_cycles cycles are
  * planned at a time and, with use_graph, captured once into a HIP graph and
  * replayed.  Each grid's result is bit-identical to vlasov_step on it alone.
+ * Batches run the local spline with the Strang splitting and no filter.
  * scratch_dev: vlasov_batch_scratch_bytes(chunk_cycles) bytes, 256-aligned.
  * Synchronises the stream before returning.  VLASOV_E_INVAL for mismatched
  * contexts or a short scratch buffer. */
@@ -232,7 +257,8 @@ int vlasov_batch_step(vlasov_ctx *const *ctxs, int32_t n, const int64_t *nsteps,
 typedef struct vlasov_server vlasov_server;
 
 typedef struct {
-    vlasov_params p;  /* storage must equal the server's; hist_cap must be 0 */
+    vlasov_params p;  /* storage must equal the server's; hist_cap must be 0; the
+                         local spline with the Strang splitting and no filter */
     int64_t nsteps;   /* >= 0 */
     int32_t keep_f;   /* nonzero: keep the final f for vlasov_poll */
     int32_t reserved;
@@ -291,7 +317,8 @@ enum {
     VLASOV_K_KICK = 4,     /* momentum advection */
     VLASOV_K_MOMENTS = 5,  /* diagnostics */
     VLASOV_K_KICK_DRIFT2 = 6,  /* kick fused with two half drifts + density partial sums */
-    VLASOV_K_COUNT = 7
+    VLASOV_K_FILTER = 7,   /* the filter along p */
+    VLASOV_K_COUNT = 8
 };
 
 /* When on, every kernel launch of the context is bracketed by HIP events on

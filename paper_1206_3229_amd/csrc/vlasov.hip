@@ -25,6 +25,25 @@ int fail(int code, const std::string &msg)
     return code;
 }
 
+// Substep sizes of the splittings, the doubles nearest to the exact values:
+// triple jump w1 = 1/(2 - 2^(1/3)), w0 = -2^(1/3)/(2 - 2^(1/3)); Suzuki
+// p = 1/(4 - 4^(1/3)) and 1 - 4p.
+int split_weights(int scheme, double *w)
+{
+    if (scheme == VLASOV_SPLIT_TRIPLE_JUMP) {
+        w[0] = w[2] = 1.3512071919596575;
+        w[1] = -1.7024143839193153;
+        return 3;
+    }
+    if (scheme == VLASOV_SPLIT_SUZUKI) {
+        w[0] = w[1] = w[3] = w[4] = 0.4144907717943757;
+        w[2] = -0.657963087177503;
+        return 5;
+    }
+    w[0] = 1.0;
+    return 1;
+}
+
 Layout layout_of(const vlasov_params &p)
 {
     Layout L{};
@@ -35,10 +54,12 @@ Layout layout_of(const vlasov_params &p)
         return at;
     };
     const size_t nx = (size_t)p.nx, np = (size_t)p.np;
-    L.drift_m = take(np * sizeof(int32_t));
-    L.drift_w = take(np * sizeof(double4));
-    L.kd_base = take((size_t)nblocks(p.np) * sizeof(int32_t));
-    L.kd_rel = take(np * sizeof(int32_t));
+    double w[MAX_SUB];
+    const size_t ns = (size_t)split_weights(p.splitting, w);
+    L.drift_m = take(ns * np * sizeof(int32_t));
+    L.drift_w = take(ns * np * sizeof(double4));
+    L.kd_base = take(ns * (size_t)nblocks(p.np) * sizeof(int32_t));
+    L.kd_rel = take(ns * np * sizeof(int32_t));
     L.part = take((size_t)nblocks(p.np) * nx * sizeof(double));
     L.rho = take(nx * sizeof(double));
     L.F = take(nx * sizeof(double));
@@ -78,6 +99,10 @@ std::string validate(const vlasov_params *p)
     if (p->spline != VLASOV_SPLINE_FD && p->spline != VLASOV_SPLINE_GS) return "unknown spline";
     if (p->spline == VLASOV_SPLINE_GS && (p->nx > vk::GS_MAX_N || p->np > vk::GS_MAX_N))
         return "the global spline takes lines of at most 4096 samples";
+    if (p->splitting < VLASOV_SPLIT_STRANG || p->splitting > VLASOV_SPLIT_SUZUKI) return "unknown splitting";
+    if (p->filter_every < 0) return "filter_every must be >= 0";
+    if (p->filter_every > 0 && !(isfinite(p->filter_strength) && p->filter_strength > 0.0 && p->filter_strength <= 1.0))
+        return "filter_strength must lie in (0, 1]";
     if (p->reserved != 0) return "reserved must be 0";
     return "";
 }
@@ -123,22 +148,23 @@ int check_launch(const char *what)
 }
 
 template <typename T, int NT>
-int launch_drift_nt(vlasov_ctx *c, int npass, bool partials)
+int launch_drift_nt(vlasov_ctx *c, int ta, int tb, bool partials)
 {
+    const int npass = tb >= 0 ? 2 : 1;
     const vlasov_params &P = c->P;
     const int tw = vk::DriftShape<NT, DRIFT_V, 0>::TW;  // columns per workgroup
     const int ntx = (int)((P.nx + tw - 1) / tw), nty = (int)c->nblk;
     const dim3 grid((unsigned)vk::xcd_grid(ntx, nty));
     const T *fin = (const T *)c->fcur();
     T *fout = (T *)c->fnext();
-    const int32_t *dm = c->at<int32_t>(c->L.drift_m);
-    const double4 *dw = c->at<double4>(c->L.drift_w);
+    const int32_t *dm1 = c->dm(ta), *dm2 = c->dm(tb >= 0 ? tb : ta);
+    const double4 *dw1 = c->dw(ta), *dw2 = c->dw(tb >= 0 ? tb : ta);
     double *part = c->at<double>(c->L.part);
     const int nx = (int)P.nx, np = (int)P.np;
     const int kid = npass == 2 ? VLASOV_K_DRIFT2 : VLASOV_K_DRIFT;
 #define DRIFT_LAUNCH(NP, BC, PT)                                                                                      \
-    launch(c, kid, vk::k_drift<T, NP, BC, PT, NT, DRIFT_V, 0, DRIFT_PF>, grid, dim3(NT), fin, fout, dm, dw, part, nx, \
-           np, ntx, nty)
+    launch(c, kid, vk::k_drift<T, NP, BC, PT, NT, DRIFT_V, 0, DRIFT_PF>, grid, dim3(NT), fin, fout, dm1, dw1, dm2,   \
+           dw2, part, nx, np, ntx, nty)
     if (P.bc_x == VLASOV_BC_PERIODIC) {
         if (npass == 2) {
             if (partials) DRIFT_LAUNCH(2, vk::BC_PERIODIC, true); else DRIFT_LAUNCH(2, vk::BC_PERIODIC, false);
@@ -159,30 +185,31 @@ int launch_drift_nt(vlasov_ctx *c, int npass, bool partials)
 }
 
 template <typename T>
-int launch_drift(vlasov_ctx *c, int npass, bool partials)
+int launch_drift(vlasov_ctx *c, int ta, int tb, bool partials)
 {
     switch (c->tune.drift_threads) {
     case 64:
-        return launch_drift_nt<T, 64>(c, npass, partials);
+        return launch_drift_nt<T, 64>(c, ta, tb, partials);
     case 256:
-        return launch_drift_nt<T, 256>(c, npass, partials);
+        return launch_drift_nt<T, 256>(c, ta, tb, partials);
     default:
-        return launch_drift_nt<T, 128>(c, npass, partials);
+        return launch_drift_nt<T, 128>(c, ta, tb, partials);
     }
 }
 
-int gs_drift(vlasov_ctx *c, bool partials);
-int gs_kick(vlasov_ctx *c);
+int gs_drift(vlasov_ctx *c, int table, bool partials);
+int gs_kick(vlasov_ctx *c, double h);
 
-int drift(vlasov_ctx *c, int npass, bool partials)
+// The half drift of table ta, then (tb >= 0) that of table tb, in one pass.
+int drift(vlasov_ctx *c, int ta, int tb, bool partials)
 {
     if (c->P.spline == VLASOV_SPLINE_GS) {  // two half drifts are two passes
-        int rc = VLASOV_OK;
-        for (int k = 0; k < npass && rc == VLASOV_OK; ++k) rc = gs_drift(c, partials && k + 1 == npass);
+        int rc = gs_drift(c, ta, partials && tb < 0);
+        if (rc == VLASOV_OK && tb >= 0) rc = gs_drift(c, tb, partials);
         return rc;
     }
-    return c->P.storage == VLASOV_F32 ? launch_drift<float>(c, npass, partials)
-                                      : launch_drift<double>(c, npass, partials);
+    return c->P.storage == VLASOV_F32 ? launch_drift<float>(c, ta, tb, partials)
+                                      : launch_drift<double>(c, ta, tb, partials);
 }
 
 // Density from the partial sums, then the model force (and magnetization).
@@ -227,7 +254,7 @@ int density_force(vlasov_ctx *c)
 }
 
 template <typename T, int KR>
-int launch_kick_r(vlasov_ctx *c)
+int launch_kick_r(vlasov_ctx *c, double h)
 {
     const vlasov_params &P = c->P;
     const int ntx = (int)((P.nx + 255) / 256), nty = (int)((P.np + KR - 1) / KR);
@@ -236,10 +263,10 @@ int launch_kick_r(vlasov_ctx *c)
     T *fout = (T *)c->fnext();
     const double *F = force_ptr(c);
     if (P.bc_p == VLASOV_BC_PERIODIC)
-        launch(c, VLASOV_K_KICK, vk::k_kick<T, vk::BC_PERIODIC, KR>, grid, dim3(256), fin, fout, F, P.dt, c->dp,
+        launch(c, VLASOV_K_KICK, vk::k_kick<T, vk::BC_PERIODIC, KR>, grid, dim3(256), fin, fout, F, h, c->dp,
                (int)P.nx, (int)P.np, ntx, nty);
     else
-        launch(c, VLASOV_K_KICK, vk::k_kick<T, vk::BC_ZERO, KR>, grid, dim3(256), fin, fout, F, P.dt, c->dp,
+        launch(c, VLASOV_K_KICK, vk::k_kick<T, vk::BC_ZERO, KR>, grid, dim3(256), fin, fout, F, h, c->dp,
                (int)P.nx, (int)P.np, ntx, nty);
     int rc = check_launch("kick");
     if (rc == VLASOV_OK) c->cur ^= 1;
@@ -247,22 +274,49 @@ int launch_kick_r(vlasov_ctx *c)
 }
 
 template <typename T>
-int launch_kick(vlasov_ctx *c)
+int launch_kick(vlasov_ctx *c, double h)
 {
     switch (c->tune.kick_rows) {
     case 8:
-        return launch_kick_r<T, 8>(c);
+        return launch_kick_r<T, 8>(c, h);
     case 16:
-        return launch_kick_r<T, 16>(c);
+        return launch_kick_r<T, 16>(c, h);
     default:
-        return launch_kick_r<T, 32>(c);
+        return launch_kick_r<T, 32>(c, h);
     }
 }
 
-int kick(vlasov_ctx *c)
+// Kick of step size h (w_k dt) with the last force.
+int kick(vlasov_ctx *c, double h)
 {
-    if (c->P.spline == VLASOV_SPLINE_GS) return gs_kick(c);
-    return c->P.storage == VLASOV_F32 ? launch_kick<float>(c) : launch_kick<double>(c);
+    if (c->P.spline == VLASOV_SPLINE_GS) return gs_kick(c, h);
+    return c->P.storage == VLASOV_F32 ? launch_kick<float>(c, h) : launch_kick<double>(c, h);
+}
+
+// The filter along p with strength sigma = filter_strength.
+template <typename T>
+int launch_filter(vlasov_ctx *c)
+{
+    const vlasov_params &P = c->P;
+    const int ntx = (int)((P.nx + 255) / 256), nty = (int)((P.np + FILTER_R - 1) / FILTER_R);
+    const dim3 grid((unsigned)vk::xcd_grid(ntx, nty));
+    const T *fin = (const T *)c->fcur();
+    T *fout = (T *)c->fnext();
+    const double cf = P.filter_strength / 256.0;
+    if (P.bc_p == VLASOV_BC_PERIODIC)
+        launch(c, VLASOV_K_FILTER, vk::k_filter_p<T, vk::BC_PERIODIC, FILTER_R>, grid, dim3(256), fin, fout, cf,
+               (int)P.nx, (int)P.np, ntx, nty);
+    else
+        launch(c, VLASOV_K_FILTER, vk::k_filter_p<T, vk::BC_ZERO, FILTER_R>, grid, dim3(256), fin, fout, cf,
+               (int)P.nx, (int)P.np, ntx, nty);
+    int rc = check_launch("filter");
+    if (rc == VLASOV_OK) c->cur ^= 1;
+    return rc;
+}
+
+int filter(vlasov_ctx *c)
+{
+    return c->P.storage == VLASOV_F32 ? launch_filter<float>(c) : launch_filter<double>(c);
 }
 
 // ---------------------------------------------------------------------------
@@ -270,13 +324,13 @@ int kick(vlasov_ctx *c)
 // rows of the transpose.
 // ---------------------------------------------------------------------------
 template <typename T>
-int gs_drift_t(vlasov_ctx *c, bool partials)
+int gs_drift_t(vlasov_ctx *c, int table, bool partials)
 {
     const vlasov_params &P = c->P;
     const T *fin = (const T *)c->fcur();
     T *fout = (T *)c->fnext();
-    const int32_t *dm = c->at<int32_t>(c->L.drift_m);
-    const double4 *dw = c->at<double4>(c->L.drift_w);
+    const int32_t *dm = c->dm(table);
+    const double4 *dw = c->dw(table);
     const double *g = c->at<double>(c->L.gs_g);
     const double *nof = nullptr;
     if (P.bc_x == VLASOV_BC_PERIODIC)
@@ -297,7 +351,7 @@ int gs_drift_t(vlasov_ctx *c, bool partials)
 }
 
 template <typename T>
-int gs_kick_t(vlasov_ctx *c)
+int gs_kick_t(vlasov_ctx *c, double h)
 {
     const vlasov_params &P = c->P;
     const int nx = (int)P.nx, np = (int)P.np;
@@ -309,27 +363,30 @@ int gs_kick_t(vlasov_ctx *c)
     const double *g = c->at<double>(c->L.gs_g);
     if (P.bc_p == VLASOV_BC_PERIODIC)
         launch(c, VLASOV_K_KICK, vk::k_gs_line<T, vk::BC_PERIODIC, true>, dim3((unsigned)nx), dim3(vk::GS_NT),
-               (const T *)B, A, np, nodm, nodw, force_ptr(c), P.dt, c->dp, g);
+               (const T *)B, A, np, nodm, nodw, force_ptr(c), h, c->dp, g);
     else
         launch(c, VLASOV_K_KICK, vk::k_gs_line<T, vk::BC_ZERO, true>, dim3((unsigned)nx), dim3(vk::GS_NT),
-               (const T *)B, A, np, nodm, nodw, force_ptr(c), P.dt, c->dp, g);
+               (const T *)B, A, np, nodm, nodw, force_ptr(c), h, c->dp, g);
     launch(c, VLASOV_K_KICK, vk::k_transpose<T>, dim3(t1), dim3(256), (const T *)A, B, nx, np);  // B = A^T
     int rc = check_launch("global-spline kick");
     if (rc == VLASOV_OK) c->cur ^= 1;
     return rc;
 }
 
-int gs_drift(vlasov_ctx *c, bool partials)
+int gs_drift(vlasov_ctx *c, int table, bool partials)
 {
-    return c->P.storage == VLASOV_F32 ? gs_drift_t<float>(c, partials) : gs_drift_t<double>(c, partials);
+    return c->P.storage == VLASOV_F32 ? gs_drift_t<float>(c, table, partials) : gs_drift_t<double>(c, table, partials);
 }
 
-int gs_kick(vlasov_ctx *c) { return c->P.storage == VLASOV_F32 ? gs_kick_t<float>(c) : gs_kick_t<double>(c); }
+int gs_kick(vlasov_ctx *c, double h)
+{
+    return c->P.storage == VLASOV_F32 ? gs_kick_t<float>(c, h) : gs_kick_t<double>(c, h);
+}
 
 // Fused kick and two half drifts (+ density partial sums) on tiles of TW
 // columns by RB density blocks.
 template <typename T, int TW, int RB>
-int launch_kick_drift_t(vlasov_ctx *c)
+int launch_kick_drift_t(vlasov_ctx *c, int ta, double h)
 {
     // whole wavefronts, about 5/8 TW threads: one first-pass run and up to two
     // kicked columns per thread
@@ -340,15 +397,16 @@ int launch_kick_drift_t(vlasov_ctx *c)
     const T *fin = (const T *)c->fcur();
     T *fout = (T *)c->fnext();
     const double *F = force_ptr(c);
-    const int32_t *dm = c->at<int32_t>(c->L.drift_m);
-    const double4 *dw = c->at<double4>(c->L.drift_w);
-    const int32_t *kbase = c->at<int32_t>(c->L.kd_base);
-    const int32_t *krel = c->at<int32_t>(c->L.kd_rel);
+    const int tb = (ta + 1) % c->nsub;
+    const int32_t *dm1 = c->dm(ta), *dm2 = c->dm(tb);
+    const double4 *dw1 = c->dw(ta), *dw2 = c->dw(tb);
+    const int32_t *kbase = c->at<int32_t>(c->L.kd_base) + (size_t)ta * (size_t)c->nblk;
+    const int32_t *krel = c->at<int32_t>(c->L.kd_rel) + (size_t)ta * (size_t)P.np;
     double *part = c->at<double>(c->L.part);
     const int nx = (int)P.nx, np = (int)P.np;
 #define KD_LAUNCH(BX, BP)                                                                                            \
     launch(c, VLASOV_K_KICK_DRIFT2, vk::k_kick_drift<T, 2, BX, BP, true, NT, TW, KD_PF, RB>, grid, dim3(NT), fin, fout, \
-           F, P.dt, c->dp, dm, dw, kbase, krel, part, nx, np, ntx, nty)
+           F, h, c->dp, dm1, dw1, dm2, dw2, kbase, krel, part, nx, np, ntx, nty)
     if (P.bc_x == VLASOV_BC_PERIODIC) {
         if (P.bc_p == VLASOV_BC_PERIODIC) KD_LAUNCH(vk::BC_PERIODIC, vk::BC_PERIODIC); else KD_LAUNCH(vk::BC_PERIODIC, vk::BC_ZERO);
     } else {
@@ -361,70 +419,80 @@ int launch_kick_drift_t(vlasov_ctx *c)
 }
 
 template <typename T, int TW>
-int launch_kick_drift_w(vlasov_ctx *c)
+int launch_kick_drift_w(vlasov_ctx *c, int ta, double h)
 {
     switch (c->kd_rb) {
     case 4:
-        return launch_kick_drift_t<T, TW, 4>(c);
+        return launch_kick_drift_t<T, TW, 4>(c, ta, h);
     case 2:
-        return launch_kick_drift_t<T, TW, 2>(c);
+        return launch_kick_drift_t<T, TW, 2>(c, ta, h);
     default:
-        return launch_kick_drift_t<T, TW, 1>(c);
+        return launch_kick_drift_t<T, TW, 1>(c, ta, h);
     }
 }
 
-// Kick followed by NPASS half drifts (+ partial sums for NPASS = 2): the
-// fused kernel for the pair of half drifts between two kicks where the
-// tables allow it and the launch shape asks for it, else the two kernels.
-int kick_then_drift(vlasov_ctx *c, int npass, bool partials)
+// Kick k (step size h), the filter if `filt`, then the half drift of table k
+// and (tb >= 0, then with partial sums) that of table tb = k + 1 mod nsub:
+// the fused kernel where the tables allow it and the launch shape asks for
+// it, else the separate kernels.
+int kick_then_drift(vlasov_ctx *c, int k, int tb, double h, bool filt)
 {
     const int w = c->tune.kick_drift_width;
-    if (npass == 2 && partials && w != 0 && c->kd_ok && c->P.spline == VLASOV_SPLINE_FD) {
+    if (tb >= 0 && !filt && w != 0 && c->kd_ok[k] && c->P.spline == VLASOV_SPLINE_FD) {
         const bool f32 = c->P.storage == VLASOV_F32;
-        if (w == 256) return f32 ? launch_kick_drift_w<float, 256>(c) : launch_kick_drift_w<double, 256>(c);
-        return f32 ? launch_kick_drift_w<float, 512>(c) : launch_kick_drift_w<double, 512>(c);
+        if (w == 256) return f32 ? launch_kick_drift_w<float, 256>(c, k, h) : launch_kick_drift_w<double, 256>(c, k, h);
+        return f32 ? launch_kick_drift_w<float, 512>(c, k, h) : launch_kick_drift_w<double, 512>(c, k, h);
     }
-    int rc = kick(c);
-    if (rc == VLASOV_OK) rc = drift(c, npass, partials);
+    int rc = kick(c, h);
+    if (rc == VLASOV_OK && filt) rc = filter(c);
+    if (rc == VLASOV_OK) rc = drift(c, k, tb, tb >= 0);
     return rc;
 }
 
-// Tables of the fused kick and drift for tiles of rb density blocks: per
-// tile the start of its kicked column range relative to the tile (two half
-// drifts), per row the offset of its window in that range.  Sets kd_ok.
+// Tables of the fused kick and drift for tiles of rb density blocks, one set
+// per pair (k, k + 1 mod nsub) of drift tables: row j's two half drifts move
+// its window by o_j = m_k,j + m_k+1,j columns; per tile the start of its
+// kicked column range relative to the tile, per row the offset of its window
+// in that range.  Sets kd_ok[k].
 void build_kd_tables(vlasov_ctx *c, int rb)
 {
     const vlasov_params &P = c->P;
     const int64_t rows = (int64_t)vk::ROWS_PER_BLOCK * rb, ntile = (c->nblk + rb - 1) / rb;
-    c->h_kd_base.assign((size_t)c->nblk, 0);
-    c->h_kd_rel.assign((size_t)P.np, 0);
-    int64_t spread = 0;
-    for (int64_t b = 0; b < ntile; ++b) {
-        const int64_t j0 = b * rows, j1 = std::min<int64_t>(P.np, j0 + rows);
-        int64_t lo = c->h_mfull[j0], hi = lo;
-        for (int64_t j = j0; j < j1; ++j) {
-            lo = std::min(lo, c->h_mfull[j]);
-            hi = std::max(hi, c->h_mfull[j]);
+    c->h_kd_base.assign((size_t)c->nsub * (size_t)c->nblk, 0);
+    c->h_kd_rel.assign((size_t)c->nsub * (size_t)P.np, 0);
+    for (int k = 0; k < c->nsub; ++k) {
+        const int64_t *ma = c->h_mfull.data() + (size_t)k * (size_t)P.np;
+        const int64_t *mb = c->h_mfull.data() + (size_t)((k + 1) % c->nsub) * (size_t)P.np;
+        int32_t *base = c->h_kd_base.data() + (size_t)k * (size_t)c->nblk;
+        int32_t *rel = c->h_kd_rel.data() + (size_t)k * (size_t)P.np;
+        int64_t spread = 0;
+        for (int64_t b = 0; b < ntile; ++b) {
+            const int64_t j0 = b * rows, j1 = std::min<int64_t>(P.np, j0 + rows);
+            int64_t lo = ma[j0] + mb[j0], hi = lo;
+            for (int64_t j = j0; j < j1; ++j) {
+                lo = std::min(lo, ma[j] + mb[j]);
+                hi = std::max(hi, ma[j] + mb[j]);
+            }
+            spread = std::max(spread, hi - lo);
+            if (hi - lo > vk::KD_SPR) continue;  // not fusable; the tables are unused
+            for (int64_t j = j0; j < j1; ++j) rel[j] = (int32_t)(ma[j] + mb[j] - lo);
+            int64_t s0 = lo - 8;
+            if (P.bc_x == VLASOV_BC_PERIODIC) {
+                s0 %= P.nx;
+                if (s0 < 0) s0 += P.nx;
+            }
+            base[b] = (int32_t)s0;
         }
-        spread = std::max(spread, hi - lo);
-        if (2 * (hi - lo) > vk::KD_SPR) continue;  // not fusable; the tables are unused
-        for (int64_t j = j0; j < j1; ++j) c->h_kd_rel[j] = (int32_t)(c->h_mfull[j] - lo);
-        int64_t s0 = 2 * lo - 8;
-        if (P.bc_x == VLASOV_BC_PERIODIC) {
-            s0 %= P.nx;
-            if (s0 < 0) s0 += P.nx;
-        }
-        c->h_kd_base[b] = (int32_t)s0;
+        c->kd_ok[k] = spread <= vk::KD_SPR;
     }
-    c->kd_ok = 2 * spread <= vk::KD_SPR;
     c->kd_rb = rb;
 }
 
 int upload_kd_tables(vlasov_ctx *c)
 {
-    HIP_TRY(hipMemcpyAsync(c->ws + c->L.kd_base, c->h_kd_base.data(), (size_t)c->nblk * sizeof(int32_t),
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.kd_base, c->h_kd_base.data(), c->h_kd_base.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->ws + c->L.kd_rel, c->h_kd_rel.data(), (size_t)c->P.np * sizeof(int32_t),
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.kd_rel, c->h_kd_rel.data(), c->h_kd_rel.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return VLASOV_OK;
@@ -506,20 +574,27 @@ int vlasov_init(const vlasov_params *p, const double *f0_host, void *f_dev, void
         c->cnt[k] = 0;
     }
 
-    // Drift line tables (eqs. step1, step4): row j moves by p_j (dt/2) / dx.
-    const double tau = 0.5 * p->dt;
-    c->h_dm.resize((size_t)p->np);
-    c->h_dw.resize((size_t)p->np);
-    c->h_mfull.resize((size_t)p->np);
-    for (int64_t j = 0; j < p->np; ++j) {
-        const double pj = p->pmin + (double)j * c->dp;
-        const vk::Foot ft = vk::foot_of_shift((pj * tau) / c->dx);
-        c->h_dm[j] = vk::reduce_offset(ft.m, p->nx, p->bc_x);
-        c->h_dw[j] = make_double4(ft.a, ft.b, ft.g, ft.d);
-        // offsets as the drift uses them: the exact foot on a periodic axis
-        // (the windows of a tile are then one contiguous range mod nx), the
-        // clamped one with zero extension
-        c->h_mfull[j] = p->bc_x == VLASOV_BC_PERIODIC ? ft.m : (int64_t)c->h_dm[j];
+    // Drift line tables (eqs. step1, step4), one per substep k: row j moves
+    // by p_j tau_k / dx with tau_k = (w_k dt)/2 (dt/2 for the Strang step).
+    c->nsub = split_weights(p->splitting, c->wsub);
+    c->steps_done = 0;
+    const size_t ntab = (size_t)c->nsub * (size_t)p->np;
+    c->h_dm.resize(ntab);
+    c->h_dw.resize(ntab);
+    c->h_mfull.resize(ntab);
+    for (int k = 0; k < c->nsub; ++k) {
+        const double tau = 0.5 * (c->wsub[k] * p->dt);
+        for (int64_t j = 0; j < p->np; ++j) {
+            const size_t e = (size_t)k * (size_t)p->np + (size_t)j;
+            const double pj = p->pmin + (double)j * c->dp;
+            const vk::Foot ft = vk::foot_of_shift((pj * tau) / c->dx);
+            c->h_dm[e] = vk::reduce_offset(ft.m, p->nx, p->bc_x);
+            c->h_dw[e] = make_double4(ft.a, ft.b, ft.g, ft.d);
+            // offsets as the drift uses them: the exact foot on a periodic axis
+            // (the windows of a tile are then one contiguous range mod nx), the
+            // clamped one with zero extension
+            c->h_mfull[e] = p->bc_x == VLASOV_BC_PERIODIC ? ft.m : (int64_t)c->h_dm[e];
+        }
     }
     build_kd_tables(c, c->tune.kick_drift_blocks);
     // Model tables.
@@ -573,10 +648,10 @@ int vlasov_init(const vlasov_params *p, const double *f0_host, void *f_dev, void
         size_t off;
         const void *src;
         size_t bytes;
-    } ups[] = {{c->L.drift_m, c->h_dm.data(), (size_t)p->np * sizeof(int32_t)},
-               {c->L.drift_w, c->h_dw.data(), (size_t)p->np * sizeof(double4)},
-               {c->L.kd_base, c->h_kd_base.data(), (size_t)c->nblk * sizeof(int32_t)},
-               {c->L.kd_rel, c->h_kd_rel.data(), (size_t)p->np * sizeof(int32_t)},
+    } ups[] = {{c->L.drift_m, c->h_dm.data(), ntab * sizeof(int32_t)},
+               {c->L.drift_w, c->h_dw.data(), ntab * sizeof(double4)},
+               {c->L.kd_base, c->h_kd_base.data(), c->h_kd_base.size() * sizeof(int32_t)},
+               {c->L.kd_rel, c->h_kd_rel.data(), c->h_kd_rel.size() * sizeof(int32_t)},
                {c->L.cs, cs.data(), nxb},
                {c->L.sn, sn.data(), nxb},
                {c->L.ringK, K.data(), nxb},
@@ -610,11 +685,19 @@ int vlasov_step(vlasov_ctx *c, int64_t nsteps)
     if (!c) return fail(VLASOV_E_INVAL, "NULL context");
     if (nsteps < 0) return fail(VLASOV_E_INVAL, "nsteps must be >= 0");
     if (nsteps == 0) return VLASOV_OK;
-    int rc = drift(c, 1, true);  // step 1 of the first step
+    const int every = c->P.filter_every;
+    int rc = drift(c, 0, -1, true);  // step 1 of the first (sub)step
     for (int64_t s = 0; rc == VLASOV_OK && s < nsteps; ++s) {
-        rc = density_force(c);  // step 2
-        // step 3, step 4 (+ step 1 of the next step)
-        if (rc == VLASOV_OK) rc = kick_then_drift(c, s + 1 < nsteps ? 2 : 1, s + 1 < nsteps);
+        const bool filtered = every > 0 && (c->steps_done + 1) % every == 0;
+        for (int k = 0; rc == VLASOV_OK && k < c->nsub; ++k) {
+            rc = density_force(c);  // step 2
+            // step 3 (+ the filter after the last kick of a filtered step),
+            // step 4, and step 1 of the next substep (or step)
+            const bool last = k + 1 == c->nsub;
+            const int tb = !last ? k + 1 : (s + 1 < nsteps ? 0 : -1);
+            if (rc == VLASOV_OK) rc = kick_then_drift(c, k, tb, c->wsub[k] * c->P.dt, filtered && last);
+        }
+        if (rc == VLASOV_OK) ++c->steps_done;
     }
     return rc;
 }
@@ -623,7 +706,7 @@ int vlasov_drift(vlasov_ctx *c, int32_t npass)
 {
     if (!c) return fail(VLASOV_E_INVAL, "NULL context");
     if (npass != 1 && npass != 2) return fail(VLASOV_E_INVAL, "npass must be 1 or 2");
-    return drift(c, npass, true);
+    return drift(c, 0, npass == 2 ? 0 : -1, true);
 }
 
 int vlasov_force(vlasov_ctx *c, double *F_host, double *mxmy_host)
@@ -664,7 +747,7 @@ int vlasov_kick(vlasov_ctx *c)
 {
     if (!c) return fail(VLASOV_E_INVAL, "NULL context");
     if (!c->have_force) return fail(VLASOV_E_STATE, "no force computed yet");
-    return kick(c);
+    return kick(c, c->wsub[0] * c->P.dt);
 }
 
 int vlasov_moments(vlasov_ctx *c, vlasov_moments_t *out)
@@ -858,7 +941,7 @@ int vlasov_profile_read(vlasov_ctx *c, int32_t kernel, double *total_ms, int64_t
 
 const char *vlasov_kernel_name(int32_t kernel)
 {
-    static const char *names[VLASOV_K_COUNT] = {"drift", "drift2", "density", "force", "kick", "moments", "kick_drift2"};
+    static const char *names[VLASOV_K_COUNT] = {"drift", "drift2", "density", "force", "kick", "moments", "kick_drift2", "filter"};
     return (kernel >= 0 && kernel < VLASOV_K_COUNT) ? names[kernel] : "";
 }
 

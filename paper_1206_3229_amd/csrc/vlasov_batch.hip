@@ -480,6 +480,8 @@ int vlasov_batch_step(vlasov_ctx *const *ctxs, int32_t n, const int64_t *nsteps,
         if (ctxs[a]->P.storage != ctxs[0]->P.storage) return fail(VLASOV_E_INVAL, "mixed storage types");
         if (ctxs[a]->stream != ctxs[0]->stream) return fail(VLASOV_E_INVAL, "contexts on different streams");
         if (ctxs[a]->P.spline != VLASOV_SPLINE_FD) return fail(VLASOV_E_INVAL, "batches run the local spline only");
+        if (ctxs[a]->P.splitting != VLASOV_SPLIT_STRANG || ctxs[a]->P.filter_every != 0)
+            return fail(VLASOV_E_INVAL, "batches run the Strang splitting without filter only");
         for (int b = 0; b < a; ++b)
             if (ctxs[b] == ctxs[a]) return fail(VLASOV_E_INVAL, "a context appears twice");
     }
@@ -503,6 +505,8 @@ int vlasov_batch_step(vlasov_ctx *const *ctxs, int32_t n, const int64_t *nsteps,
         if ((rc = eng.chunk(ms)) != VLASOV_OK) break;
     }
     eng.release();
+    if (rc == VLASOV_OK)
+        for (int a = 0; a < n; ++a) ctxs[a]->steps_done += nsteps[a];
     return rc;
 }
 
@@ -548,6 +552,8 @@ int vlasov_submit(vlasov_server *s, const vlasov_request *r, const double *f0_ho
     if (r->p.storage != s->storage) return fail(VLASOV_E_INVAL, "request storage differs from the server's");
     if (r->p.hist_cap != 0) return fail(VLASOV_E_INVAL, "requests keep no magnetization history");
     if (r->p.spline != VLASOV_SPLINE_FD) return fail(VLASOV_E_INVAL, "the server runs the local spline only");
+    if (r->p.splitting != VLASOV_SPLIT_STRANG || r->p.filter_every != 0)
+        return fail(VLASOV_E_INVAL, "the server runs the Strang splitting without filter only");
     if (r->nsteps < 0) return fail(VLASOV_E_INVAL, "nsteps must be >= 0");
     const size_t bytes = vlasov_request_footprint(&r->p);
     if (bytes > s->arena_bytes - s->table_bytes) return fail(VLASOV_E_NOMEM, "request larger than the arena");

@@ -35,8 +35,18 @@ constexpr int DRIFT_NT = 128, DRIFT_V = 2, DRIFT_PF = 4;
 template <typename T> constexpr int kick_rows() { return sizeof(T) == 8 ? 16 : 32; }
 // fused kick and drift: default tile width, rows requested ahead by the kick
 constexpr int KD_TW = 256, KD_RB = 1, KD_PF = 4;
+// rows per thread of the filter along p
+constexpr int FILTER_R = 16;
+// substeps of a step at most (the splittings of vlasov_splitting)
+constexpr int MAX_SUB = 5;
 
-// Workspace layout (byte offsets, each 256-aligned).
+// Sizes w_k of the substeps of one step (in units of dt); returns their number.
+int split_weights(int scheme, double *w);
+
+// Workspace layout (byte offsets, each 256-aligned).  The drift tables
+// (drift_m, drift_w) hold one table per substep (np rows each), the fused
+// kick-drift tables one per pair of consecutive substeps (kd_base nblk
+// entries, kd_rel np entries each).
 struct Layout {
     size_t drift_m, drift_w, kd_base, kd_rel, part, rho, F, Fext, cs, sn, ringK, ringV, mxmy, hist, hcount, mom_out,
         mom_col, mom_phi, gs_g;
@@ -69,9 +79,14 @@ struct vlasov_ctx {
     std::vector<double4> h_dw;
     std::vector<int64_t> h_mfull;  // drift foot offset per row, as the fused tables need it
     std::vector<int32_t> h_kd_base, h_kd_rel;
-    // kick and the two half drifts after it can run fused on tiles of
-    // kd_rb blocks (drift shifts of every tile within the kicked halo)
-    bool kd_ok;
+    // substeps of a step (splitting) and steps taken since init (filter schedule)
+    int nsub;
+    double wsub[vlasov_detail::MAX_SUB];
+    int64_t steps_done;
+    // kick k and the two half drifts after it (tables k, k+1 mod nsub) can run
+    // fused on tiles of kd_rb blocks (drift shifts of every tile within the
+    // kicked halo)
+    bool kd_ok[vlasov_detail::MAX_SUB];
     int kd_rb;
     // profiling
     bool prof;
@@ -85,6 +100,9 @@ struct vlasov_ctx {
     int64_t cnt[VLASOV_K_COUNT];
 
     template <typename U> U *at(size_t off) const { return reinterpret_cast<U *>(ws + off); }
+    // drift table of substep k
+    const int32_t *dm(int k) const { return at<int32_t>(L.drift_m) + (size_t)k * (size_t)P.np; }
+    const double4 *dw(int k) const { return at<double4>(L.drift_w) + (size_t)k * (size_t)P.np; }
     void *fcur() const { return f[cur]; }
     void *fnext() const { return f[cur ^ 1]; }
 };

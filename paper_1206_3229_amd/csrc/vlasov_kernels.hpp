@@ -198,9 +198,9 @@ __device__ __forceinline__ void store_run(T *row, int i, int nx, const T (&o)[V]
 
 // ---------------------------------------------------------------------------
 // Steps 1 and 4 (eqs. step1, step4): drift along x, row j shifted by the
-// constant p_j tau/dx cells.  NPASS = 2 applies the half drift twice (the
-// second half drift of one step and the first of the next), keeping the
-// intermediate row in LDS.  One workgroup of NT threads: TW consecutive
+// constant p_j tau/dx cells.  NPASS = 2 applies two half drifts in turn (the
+// second half drift of one (sub)step and the first of the next, tables 1 and
+// 2: equal for the Strang splitting), keeping the intermediate row in LDS.  One workgroup of NT threads: TW consecutive
 // columns of a block of 16 consecutive rows, runs of V adjacent columns per
 // thread; TW = V NT - TRIM (a trim keeps the TW + 9 intermediate values of the
 // two-pass form within one run per thread).  Rows stream through two LDS window
@@ -210,8 +210,9 @@ __device__ __forceinline__ void store_run(T *row, int i, int nx, const T (&o)[V]
 // 16 output rows (density partial sums).
 // ---------------------------------------------------------------------------
 template <typename T, int BC, int NPASS, int TW, int NT, int NLD>
-__device__ __forceinline__ void load_window(const T *__restrict__ fin, const int32_t *__restrict__ dm, int j, int i0,
-                                            int nx, T (&v)[NLD], uint32_t &inside)
+__device__ __forceinline__ void load_window(const T *__restrict__ fin, const int32_t *__restrict__ dm1,
+                                            const int32_t *__restrict__ dm2, int j, int i0, int nx, T (&v)[NLD],
+                                            uint32_t &inside)
 {
     // Branch-free: every thread issues NLD loads at valid addresses (periodic
     // positions wrapped, zero-extended ones clamped; slots past the window
@@ -221,7 +222,7 @@ __device__ __forceinline__ void load_window(const T *__restrict__ fin, const int
     // sits next to its load and the loads of the rows requested ahead stay in
     // flight.
     const T *row = fin + (size_t)j * nx;
-    int base = i0 + NPASS * dm[j] - 4 * NPASS;
+    int base = i0 + (NPASS == 2 ? dm1[j] + dm2[j] : dm1[j]) - 4 * NPASS;
     if (BC == BC_PERIODIC) base = wrap(base, nx);
     inside = 0;
 #pragma unroll
@@ -274,7 +275,8 @@ struct DriftShape {
 // access), which lets the loads requested ahead stay in flight.
 template <typename T, int NPASS, int BC, bool PARTIALS, int NT, int V, int TRIM, int PF, bool FULL>
 __device__ __forceinline__ void drift_tile(const T *__restrict__ fin, T *__restrict__ fout,
-                                           const int32_t *__restrict__ dm, const double4 *__restrict__ dw,
+                                           const int32_t *__restrict__ dm1, const double4 *__restrict__ dw1,
+                                           const int32_t *__restrict__ dm2, const double4 *__restrict__ dw2,
                                            double *__restrict__ part, int nx, int np, int tx, int ty, T *win0,
                                            T *win1, T *mid)
 {
@@ -299,7 +301,7 @@ __device__ __forceinline__ void drift_tile(const T *__restrict__ fin, T *__restr
     static_assert(NLD <= 32, "one bit per loaded slot");
 #pragma unroll
     for (int r = 0; r < PF; ++r)
-        if (FULL || r < nr) load_window<T, BC, NPASS, TW, NT, NLD>(fin, dm, j0 + r, i0, nx, v[r], inside[r]);
+        if (FULL || r < nr) load_window<T, BC, NPASS, TW, NT, NLD>(fin, dm1, dm2, j0 + r, i0, nx, v[r], inside[r]);
 
     const int i = i0 + V * t;                // first of this thread's V columns
     const bool own = FULL || V * t < TW;     // trailing threads own no output when TRIM > 0
@@ -318,18 +320,22 @@ __device__ __forceinline__ void drift_tile(const T *__restrict__ fin, T *__restr
                 wrow[k < NLD - 1 || s < WIN ? s : LDW] = BC == BC_PERIODIC || (inside[r % PF] >> k & 1u) ? x : T(0);
             }
             if (FULL ? r + PF < R : r + PF < nr)
-                load_window<T, BC, NPASS, TW, NT, NLD>(fin, dm, j0 + r + PF, i0, nx, v[r % PF], inside[r % PF]);
+                load_window<T, BC, NPASS, TW, NT, NLD>(fin, dm1, dm2, j0 + r + PF, i0, nx, v[r % PF],
+                                                       inside[r % PF]);
             __syncthreads();
             const int j = j0 + r;
-            const double4 w = dw[j];
+            const double4 w = (NPASS == 2 ? dw2 : dw1)[j];
             const T a = (T)w.x, b = (T)w.y, g = (T)w.z, d = (T)w.w;
             const T *src = wrow;
             if (NPASS == 2) {
-                // first half drift at positions i0 + m - 4 + q, q in [0, TW + 9)
-                const int m = dm[j];
+                // first half drift (table 1) at the positions i0 + m - 4 + q,
+                // q in [0, TW + 9), that the second (table 2, offset m) reads
+                const int m = dm2[j];
+                const double4 w1 = dw1[j];
+                const T a1 = (T)w1.x, b1 = (T)w1.y, g1 = (T)w1.z, d1 = (T)w1.w;
                 for (int u = t; u < NRUN1; u += NT) {
                     T o[V];
-                    spline_run<T, V>(src, u, a, b, g, d, o);
+                    spline_run<T, V>(src, u, a1, b1, g1, d1, o);
                     if (BC == BC_ZERO) {
                         const int q = i0 + m - 4 + V * u;
 #pragma unroll
@@ -379,23 +385,25 @@ __device__ __forceinline__ void drift_tile(const T *__restrict__ fin, T *__restr
 // Full tiles take the straight-line form, edge tiles the guarded one.
 template <typename T, int NPASS, int BC, bool PARTIALS, int NT, int V, int TRIM, int PF>
 __device__ __forceinline__ void drift_tile_any(const T *__restrict__ fin, T *__restrict__ fout,
-                                               const int32_t *__restrict__ dm, const double4 *__restrict__ dw,
+                                               const int32_t *__restrict__ dm1, const double4 *__restrict__ dw1,
+                                               const int32_t *__restrict__ dm2, const double4 *__restrict__ dw2,
                                                double *__restrict__ part, int nx, int np, int tx, int ty, T *win0,
                                                T *win1, T *mid)
 {
     constexpr int TW = DriftGeom<NPASS, NT, V, TRIM>::TW;
     const bool full = (ty + 1) * ROWS_PER_BLOCK <= np && (tx + 1) * TW <= nx && (nx & 1) == 0;
     if (full)
-        drift_tile<T, NPASS, BC, PARTIALS, NT, V, TRIM, PF, true>(fin, fout, dm, dw, part, nx, np, tx, ty, win0, win1,
-                                                                  mid);
+        drift_tile<T, NPASS, BC, PARTIALS, NT, V, TRIM, PF, true>(fin, fout, dm1, dw1, dm2, dw2, part, nx, np, tx, ty,
+                                                                  win0, win1, mid);
     else
-        drift_tile<T, NPASS, BC, PARTIALS, NT, V, TRIM, PF, false>(fin, fout, dm, dw, part, nx, np, tx, ty, win0, win1,
-                                                                   mid);
+        drift_tile<T, NPASS, BC, PARTIALS, NT, V, TRIM, PF, false>(fin, fout, dm1, dw1, dm2, dw2, part, nx, np, tx, ty,
+                                                                   win0, win1, mid);
 }
 
 template <typename T, int NPASS, int BC, bool PARTIALS, int NT, int V, int TRIM, int PF>
 static __global__ __launch_bounds__(NT) void k_drift(const T *__restrict__ fin, T *__restrict__ fout,
-                                              const int32_t *__restrict__ dm, const double4 *__restrict__ dw,
+                                              const int32_t *__restrict__ dm1, const double4 *__restrict__ dw1,
+                                              const int32_t *__restrict__ dm2, const double4 *__restrict__ dw2,
                                               double *__restrict__ part, int nx, int np, int ntx, int nty)
 {
     using G = DriftGeom<NPASS, NT, V, TRIM>;
@@ -403,7 +411,8 @@ static __global__ __launch_bounds__(NT) void k_drift(const T *__restrict__ fin, 
     __shared__ __attribute__((aligned(16))) T mid[G::LDM];
     int tx, ty;
     if (!xcd_tile(ntx, nty, tx, ty)) return;
-    drift_tile_any<T, NPASS, BC, PARTIALS, NT, V, TRIM, PF>(fin, fout, dm, dw, part, nx, np, tx, ty, win[0], win[1], mid);
+    drift_tile_any<T, NPASS, BC, PARTIALS, NT, V, TRIM, PF>(fin, fout, dm1, dw1, dm2, dw2, part, nx, np, tx, ty, win[0],
+                                                            win[1], mid);
 }
 
 // ---------------------------------------------------------------------------
@@ -449,6 +458,41 @@ static __global__ __launch_bounds__(256) void k_kick(const T *__restrict__ fin, 
 }
 
 // ---------------------------------------------------------------------------
+// The filter along p, after the last kick of a filtered step (the filtering
+// the conclusions name as an extension): out_j = f_j - c s_j with c =
+// sigma/256 and s_j = sum_m b_m f_{j+m}, b the binomial weights (1, -8, 28,
+// -56, 70, ...) of the eighth central difference, symmetric pairs added
+// first and accumulated from the outermost pair inwards.  One thread per
+// column and R consecutive rows, the R + 8 samples held in registers.
+// ---------------------------------------------------------------------------
+template <typename T, int BC, int R>
+static __global__ __launch_bounds__(256) void k_filter_p(const T *__restrict__ fin, T *__restrict__ fout, double c,
+                                                  int nx, int np, int ntx, int nty)
+{
+    int tx, ty;
+    if (!xcd_tile(ntx, nty, tx, ty)) return;
+    const int i = tx * 256 + threadIdx.x;
+    if (i >= nx) return;
+    const int j0 = ty * R;
+    const T *col = fin + i;
+    T w[R + 8];
+#pragma unroll
+    for (int s = 0; s < R + 8; ++s) w[s] = sample<T, BC>(col, j0 - 4 + s, np, (size_t)nx);
+    const T cc = (T)c;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = j0 + r;
+        const T *q = w + r + 4;
+        T sm = q[-4] + q[4];
+        sm = vfma(T(-8), q[-3] + q[3], sm);
+        sm = vfma(T(28), q[-2] + q[2], sm);
+        sm = vfma(T(-56), q[-1] + q[1], sm);
+        sm = vfma(T(70), q[0], sm);
+        if (j < np) fout[(size_t)j * nx + i] = vfma(-cc, sm, q[0]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Step 3 fused with the drift that follows it (step 4, and with NPASS = 2 also
 // step 1 of the next step).  Once the force is known nothing global separates
 // the kick of a row from its drift, so one workgroup kicks the columns its
@@ -457,16 +501,16 @@ static __global__ __launch_bounds__(256) void k_kick(const T *__restrict__ fin, 
 // the separate kick and drift, so results are identical bit for bit.
 //
 // Tile: RB consecutive density blocks (16 RB rows) by TW output columns, NT
-// threads.  The drift window of row j starts at column i0 + NPASS m_j -
-// 4 NPASS; over the tile these windows lie in the KW = WIN + SPR kicked
-// columns starting at i0 + kbase (kbase = NPASS min_j m_j - 4 NPASS, reduced
-// mod nx on a periodic x axis), row j's window at offset NPASS krel_j, krel_j
-// = m_j - min m.  A grid whose tiles need NPASS krel > SPR takes the separate
-// kernels.  Thread t kicks the columns kappa = t + k NT (k < KC) of that
+// threads.  The drift window of row j starts at column i0 + o_j - 4 NPASS,
+// o_j the sum of the row's drift offsets (m1_j + m2_j, or m1_j for NPASS =
+// 1); over the tile these windows lie in the KW = WIN + SPR kicked columns
+// starting at i0 + kbase (kbase = min_j o_j - 4 NPASS, reduced mod nx on a
+// periodic x axis), row j's window at offset krel_j = o_j - min o.  A grid
+// whose tiles need krel > SPR takes the separate kernels.  Thread t kicks the columns kappa = t + k NT (k < KC) of that
 // range, each from a sliding register window of its column (the kick of row
 // r needs the samples r - 4 + m .. r + 5 + m), requested PF rows ahead and
 // carried across the blocks of the tile, and writes the kicked row into the
-// LDS window of the drift at kappa - NPASS krel_j.  The taller the tile, the
+// LDS window of the drift at kappa - krel_j.  The taller the tile, the
 // smaller the share of the 10 halo rows the kick reads above and below it.
 // ---------------------------------------------------------------------------
 constexpr int KD_SPR = 8;
@@ -485,7 +529,8 @@ template <typename T, int NPASS, int BCX, int BCP, bool PARTIALS, int NT, int TW
           bool FULL>
 __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__restrict__ fout,
                                                 const double *__restrict__ F, double dt, double dp,
-                                                const int32_t *__restrict__ dm, const double4 *__restrict__ dw,
+                                                const int32_t *__restrict__ dm1, const double4 *__restrict__ dw1,
+                                                const int32_t *__restrict__ dm2, const double4 *__restrict__ dw2,
                                                 const int32_t *__restrict__ kbase, const int32_t *__restrict__ krel,
                                                 double *__restrict__ part, int nx, int np, int tx, int ty, T *win0,
                                                 T *win1, T *mid)
@@ -588,7 +633,7 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
                 const int j = jb + r;
                 T *wrow = (r & 1) ? win1 : win0;
                 settle(r + 9);
-                const int rel = NPASS * krel[j];
+                const int rel = krel[j];
 #pragma unroll
                 for (int k = 0; k < KC; ++k) {
                     const T Dk1 = second_diff(w[k] + r + 5);
@@ -602,15 +647,17 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
                 // or wrapped addresses; unused after the last block)
                 if (r + 10 + PF < NS && (RB > 1 || r + 10 + PF < R + 10)) request(r + 10 + PF);
                 __syncthreads();
-                const double4 wd = dw[j];
+                const double4 wd = (NPASS == 2 ? dw2 : dw1)[j];
                 const T a = (T)wd.x, b = (T)wd.y, g = (T)wd.z, d = (T)wd.w;
                 const T *src = wrow;
                 if (NPASS == 2) {
-                    // first half drift at positions i0 + m - 4 + q, q in [0, TW + 9)
-                    const int m = dm[j];
+                    // first half drift (table 1) at positions i0 + m - 4 + q,
+                    // q in [0, TW + 9), m the offset of the second
+                    const int m = dm2[j];
+                    const double4 w1 = dw1[j];
                     if (t < NRUN1) {
                         T o[V];
-                        spline_run<T, V>(src, t, a, b, g, d, o);
+                        spline_run<T, V>(src, t, (T)w1.x, (T)w1.y, (T)w1.z, (T)w1.w, o);
                         if (BCX == BC_ZERO) {
                             const int q = i0 + m - 4 + V * t;
 #pragma unroll
@@ -673,8 +720,10 @@ template <typename T, int NPASS, int BCX, int BCP, bool PARTIALS, int NT, int TW
           int UB = 1>
 static __global__ __launch_bounds__(NT) void k_kick_drift(const T *__restrict__ fin, T *__restrict__ fout,
                                                    const double *__restrict__ F, double dt, double dp,
-                                                   const int32_t *__restrict__ dm,
-                                                   const double4 *__restrict__ dw,
+                                                   const int32_t *__restrict__ dm1,
+                                                   const double4 *__restrict__ dw1,
+                                                   const int32_t *__restrict__ dm2,
+                                                   const double4 *__restrict__ dw2,
                                                    const int32_t *__restrict__ kbase,
                                                    const int32_t *__restrict__ krel, double *__restrict__ part,
                                                    int nx, int np, int ntx, int nty)
@@ -687,10 +736,10 @@ static __global__ __launch_bounds__(NT) void k_kick_drift(const T *__restrict__ 
     const bool full = (ty + 1) * (ROWS_PER_BLOCK * RB) <= np && (tx + 1) * TW <= nx && (nx & 1) == 0;
     if (full)
         kick_drift_tile<T, NPASS, BCX, BCP, PARTIALS, NT, TW, PF, RB, VR, UB, true>(
-            fin, fout, F, dt, dp, dm, dw, kbase, krel, part, nx, np, tx, ty, win[0], win[1], mid);
+            fin, fout, F, dt, dp, dm1, dw1, dm2, dw2, kbase, krel, part, nx, np, tx, ty, win[0], win[1], mid);
     else
         kick_drift_tile<T, NPASS, BCX, BCP, PARTIALS, NT, TW, PF, RB, VR, UB, false>(
-            fin, fout, F, dt, dp, dm, dw, kbase, krel, part, nx, np, tx, ty, win[0], win[1], mid);
+            fin, fout, F, dt, dp, dm1, dw1, dm2, dw2, kbase, krel, part, nx, np, tx, ty, win[0], win[1], mid);
 }
 
 // ---------------------------------------------------------------------------
@@ -1304,7 +1353,8 @@ static __global__ __launch_bounds__(NT) void kb_drift(const GridDesc *__restrict
         T *fout = (T *)g.f[cur ^ 1];
         __syncthreads();
 #define BD(NP, BC, PT)                                                                                               \
-    drift_tile_any<T, NP, BC, PT, NT, V, 0, PF>(fin, fout, g.dm, g.dw, g.part, g.nx, g.np, tx, ty, win[0], win[1], mid)
+    drift_tile_any<T, NP, BC, PT, NT, V, 0, PF>(fin, fout, g.dm, g.dw, g.dm, g.dw, g.part, g.nx, g.np, tx, ty, win[0],   \
+                                                win[1], mid)
         if (g.bc_x == BC_PERIODIC) {
             if (kind == DRIFT_PAIR)
                 BD(2, BC_PERIODIC, true);

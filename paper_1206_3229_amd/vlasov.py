@@ -19,7 +19,7 @@ OK, PENDING = 0, 1
 E_INVAL, E_NOMEM, E_HIP, E_STATE, E_NOTFOUND, E_NONFINITE = -1, -2, -3, -4, -5, -6
 
 K_DRIFT, K_DRIFT2, K_DENSITY, K_FORCE, K_KICK, K_MOMENTS, K_KICK_DRIFT2 = range(7)
-KERNELS = ("drift", "drift2", "density", "force", "kick", "moments", "kick_drift2")
+KERNELS = ("drift", "drift2", "density", "force", "kick", "moments", "kick_drift2", "filter")
 
 
 class VlasovError(RuntimeError):
@@ -33,7 +33,8 @@ class Params(C.Structure):
                 ("nx", C.c_int64), ("np", C.c_int64),
                 ("xmin", C.c_double), ("xmax", C.c_double), ("pmin", C.c_double), ("pmax", C.c_double),
                 ("dt", C.c_double), ("ring_eps", C.c_double), ("sheet_G", C.c_double),
-                ("hist_cap", C.c_int64), ("spline", C.c_int32), ("reserved", C.c_int32)]
+                ("hist_cap", C.c_int64), ("spline", C.c_int32), ("splitting", C.c_int32),
+                ("filter_every", C.c_int32), ("reserved", C.c_int32), ("filter_strength", C.c_double)]
 
 
 class Moments(C.Structure):
@@ -129,7 +130,9 @@ def to_params(p, hist_cap: int = 0) -> Params:
     """From paper_1206_3229_amd.inputs.Params."""
     return Params(int(p.model), int(p.storage), int(p.bc_x), int(p.bc_p), int(p.nx), int(p.np_),
                   float(p.xmin), float(p.xmax), float(p.pmin), float(p.pmax), float(p.dt),
-                  float(p.ring_eps), float(p.sheet_G), int(hist_cap), int(getattr(p, "spline", 0)), 0)
+                  float(p.ring_eps), float(p.sheet_G), int(hist_cap), int(getattr(p, "spline", 0)),
+                  int(getattr(p, "splitting", 0)), int(getattr(p, "filter_every", 0)), 0,
+                  float(getattr(p, "filter_strength", 0.0)))
 
 
 def _dptr(a: np.ndarray):

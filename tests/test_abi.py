@@ -37,7 +37,8 @@ def test_every_declared_symbol_is_exported(lib):
 def _params(**kw):
     from paper_1206_3229_amd import vlasov as V
     d = dict(model=0, storage=0, bc_x=0, bc_p=0, nx=64, np=32, xmin=-math.pi, xmax=math.pi, pmin=-2.0, pmax=2.0,
-             dt=0.1, ring_eps=0.01, sheet_G=1.0, hist_cap=10, spline=0, reserved=0)
+             dt=0.1, ring_eps=0.01, sheet_G=1.0, hist_cap=10, spline=0, splitting=0, filter_every=0, reserved=0,
+             filter_strength=0.0)
     d.update(kw)
     return V.Params(*[d[n] for n, _ in V.Params._fields_])
 
@@ -58,6 +59,8 @@ def test_buffer_sizes(lib):
     dict(dt=0.0), dict(dt=float("nan")), dict(pmin=float("inf")), dict(model=0, bc_x=1),
     dict(model=1, ring_eps=0.0), dict(hist_cap=-1), dict(nx=1 << 16, np=1 << 16),
     dict(spline=2), dict(spline=1, nx=8192), dict(reserved=1),
+    dict(splitting=3), dict(splitting=-1), dict(filter_every=-1), dict(filter_every=1, filter_strength=0.0),
+    dict(filter_every=2, filter_strength=1.5), dict(filter_every=1, filter_strength=float("nan")),
 ])
 def test_invalid_parameters_rejected_on_host(lib, bad):
     p = _params(**bad)
@@ -80,8 +83,8 @@ def test_null_and_misaligned_pointers_rejected(lib):
 
 
 def test_kernel_names(lib):
-    assert [lib.vlasov_kernel_name(k).decode() for k in range(8)] == \
-        ["drift", "drift2", "density", "force", "kick", "moments", "kick_drift2", ""]
+    assert [lib.vlasov_kernel_name(k).decode() for k in range(9)] == \
+        ["drift", "drift2", "density", "force", "kick", "moments", "kick_drift2", "filter", ""]
 
 
 def test_tuning_candidates_cover_separate_and_fused(lib):
@@ -91,3 +94,12 @@ def test_tuning_candidates_cover_separate_and_fused(lib):
     assert sum(1 for c in cands if c[2] == 0) == 9
     assert {c[2] for c in cands} == {0, 256, 512}
     assert {(c[2], c[3]) for c in cands if c[2]} == {(w, b) for w in (256, 512) for b in (1, 2, 4)}
+
+
+def test_workspace_holds_a_drift_table_per_substep(lib):
+    base = lib.vlasov_workspace_bytes(C.byref(_params(np=4096)))
+    tj = lib.vlasov_workspace_bytes(C.byref(_params(np=4096, splitting=1)))
+    sz = lib.vlasov_workspace_bytes(C.byref(_params(np=4096, splitting=2)))
+    # per substep: m (4 B) and weights (32 B) per row, and the fused tables (4 B per row and per block)
+    assert tj - base >= 2 * 4096 * (4 + 32 + 4)
+    assert sz - base >= 4 * 4096 * (4 + 32 + 4)
