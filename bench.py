@@ -260,6 +260,24 @@ def serving(V, torch, nreq, seed=0, arena_bytes=2 << 30, max_slots=48, chunk=16)
     }
 
 
+def variant_rate(V, torch, workload: str, steps: int, shape, **overrides) -> dict:
+    """Throughput of the workload with other solver options (a full step each)."""
+    p, f0, _ = WORKLOADS[workload]()
+    p = I.Params(**{**p.as_dict(), **overrides})
+    s = V.Solver(p, f0)
+    if shape:
+        s.set_tuning(*shape)
+    s.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    s.close()
+    return {"options": overrides, "value": p.nx * p.np_ * steps / t, "unit": "grid-point updates/s",
+            "ms_per_step": t / steps * 1e3, "steps": steps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +288,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-storage leg")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-kernel ceiling")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 leg and the copy ceiling")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the global-spline, fourth-order-splitting and filter legs")
     ap.add_argument("--serve-requests", type=int, default=512, help="requests of the serving leg (0: skip)")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch shapes")
     ap.add_argument("--shape", default=None,
@@ -351,21 +371,14 @@ def main():
                                    "ms_per_step": secs32 / args.steps * 1e3,
                                    "kernels_us": {k: (v[0] / v[1] * 1e3 if v[1] else None)
                                                   for k, v in prof32.items()}}
-    if not args.no_extras:
+    if not (args.no_extras or args.no_variants):
+        steps_v = max(2, args.steps // 10)
         # the paper's baseline interpolation (global spline, eq. tridiagsys) on the same workload
-        pg, fg, _ = WORKLOADS[args.workload]()
-        pg = I.Params(**{**pg.as_dict(), "spline": I.SPLINE_GS})
-        sg = V.Solver(pg, fg)
-        gsteps = max(1, args.steps // 10)
-        sg.step(2)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sg.step(gsteps)
-        torch.cuda.synchronize()
-        tg = time.perf_counter() - t0
-        sg.close()
-        out["global_spline"] = {"value": pg.nx * pg.np_ * gsteps / tg, "unit": "grid-point updates/s",
-                                "ms_per_step": tg / gsteps * 1e3, "steps": gsteps}
+        out["global_spline"] = variant_rate(V, torch, args.workload, steps_v, shape, spline=I.SPLINE_GS)
+        # the higher-order splitting and the filter of the conclusions
+        out["triple_jump"] = variant_rate(V, torch, args.workload, steps_v, shape, splitting=I.SPLIT_TRIPLE_JUMP)
+        out["filter_every_step"] = variant_rate(V, torch, args.workload, steps_v, shape, filter_every=1,
+                                                filter_strength=1.0)
     if not args.no_copy:
         out["copy_ceiling_GBps"] = copy_ceiling(torch, V)
     if args.no_extras:

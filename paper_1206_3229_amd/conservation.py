@@ -12,6 +12,8 @@ the x box, periodic in p.  The moments are sampled every `every` steps (the
 run is split into calls of that many steps, which changes no result).
 
     python -m paper_1206_3229_amd.conservation [--t-end 100] [--sizes 256,512]
+        [--splines fd,gs] [--splittings strang,triple_jump,suzuki]
+        [--filter-every K --filter-strength S]
 """
 from __future__ import annotations
 
@@ -23,9 +25,16 @@ import time
 from . import inputs as I
 
 
-def sheet_table_params(n: int, dt: float, storage: int = I.STORAGE_F64, spline: int = I.SPLINE_FD) -> I.Params:
+SPLINES = {"fd": I.SPLINE_FD, "gs": I.SPLINE_GS}
+SPLITTINGS = {"strang": I.SPLIT_STRANG, "triple_jump": I.SPLIT_TRIPLE_JUMP, "suzuki": I.SPLIT_SUZUKI}
+
+
+def sheet_table_params(n: int, dt: float, storage: int = I.STORAGE_F64, spline: int = I.SPLINE_FD,
+                       splitting: int = I.SPLIT_STRANG, filter_every: int = 0,
+                       filter_strength: float = 0.0) -> I.Params:
     return I.Params(I.MODEL_SHEET, n, n, -2.0, 2.0, -2.0, 2.0, dt, bc_x=I.BC_ZERO, storage=storage,
-                    sheet_G=1.0 / (2.0 * math.pi), spline=spline)
+                    sheet_G=1.0 / (2.0 * math.pi), spline=spline, splitting=splitting,
+                    filter_every=filter_every, filter_strength=filter_strength)
 
 
 def track(V, params, f0, nsteps: int, every: int) -> dict:
@@ -52,19 +61,24 @@ def track(V, params, f0, nsteps: int, every: int) -> dict:
 
 
 def paper_tables(V, sizes=(256, 512, 1024, 2048), dts=(0.01, 0.1), t_end: float = 100.0,
-                 samples: int = 100, storage: int = I.STORAGE_F64, splines=(I.SPLINE_FD, I.SPLINE_GS)) -> list[dict]:
-    """Both columns of the tables: the local (FD) and the global (GS) spline."""
+                 samples: int = 100, storage: int = I.STORAGE_F64, splines=("fd", "gs"),
+                 splittings=("strang",), filter_every: int = 0, filter_strength: float = 0.0) -> list[dict]:
+    """Both columns of the tables (the local (fd) and the global (gs)
+    spline), for each time splitting."""
     rows = []
     for dt in dts:
         nsteps = int(round(t_end / dt))
         every = max(1, nsteps // samples)
         for n in sizes:
-            for spline in splines:
-                p = sheet_table_params(n, dt, storage, spline)
-                f0 = I.waterbag(p, 1.0, 0.5)
-                r = track(V, p, f0, nsteps, every)
-                rows.append({"n": n, "dt": dt, "spline": "gs" if spline == I.SPLINE_GS else "fd",
-                             "t_end": t_end, **r})
+            for split in splittings:
+                for spline in splines:
+                    p = sheet_table_params(n, dt, storage, SPLINES[spline], SPLITTINGS[split], filter_every,
+                                           filter_strength)
+                    f0 = I.waterbag(p, 1.0, 0.5)
+                    r = track(V, p, f0, nsteps, every)
+                    rows.append({"n": n, "dt": dt, "spline": spline, "splitting": split,
+                                 "filter_every": filter_every, "filter_strength": filter_strength,
+                                 "t_end": t_end, **r})
     return rows
 
 
@@ -75,6 +89,10 @@ def main():
     ap.add_argument("--dts", default="0.01,0.1")
     ap.add_argument("--samples", type=int, default=100)
     ap.add_argument("--storage", type=int, default=0)
+    ap.add_argument("--splines", default="fd,gs")
+    ap.add_argument("--splittings", default="strang")
+    ap.add_argument("--filter-every", type=int, default=0)
+    ap.add_argument("--filter-strength", type=float, default=0.0)
     args = ap.parse_args()
     import torch
     from . import vlasov as V
@@ -82,7 +100,8 @@ def main():
         raise SystemExit("conservation: no GPU visible")
     V.load()
     rows = paper_tables(V, tuple(int(v) for v in args.sizes.split(",")), tuple(float(v) for v in args.dts.split(",")),
-                        args.t_end, args.samples, args.storage)
+                        args.t_end, args.samples, args.storage, tuple(args.splines.split(",")),
+                        tuple(args.splittings.split(",")), args.filter_every, args.filter_strength)
     for r in rows:
         print(json.dumps(r), flush=True)
 

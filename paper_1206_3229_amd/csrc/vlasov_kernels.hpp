@@ -634,6 +634,11 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
                 T *wrow = (r & 1) ? win1 : win0;
                 settle(r + 9);
                 const int rel = krel[j];
+                // the row's drift tables, requested before the kick so that
+                // their latency hides behind it
+                const double4 wd = (NPASS == 2 ? dw2 : dw1)[j];
+                const double4 w1 = NPASS == 2 && dw1 != dw2 ? dw1[j] : wd;  // one table: Strang
+                const int m = NPASS == 2 ? dm2[j] : 0;
 #pragma unroll
                 for (int k = 0; k < KC; ++k) {
                     const T Dk1 = second_diff(w[k] + r + 5);
@@ -647,14 +652,11 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
                 // or wrapped addresses; unused after the last block)
                 if (r + 10 + PF < NS && (RB > 1 || r + 10 + PF < R + 10)) request(r + 10 + PF);
                 __syncthreads();
-                const double4 wd = (NPASS == 2 ? dw2 : dw1)[j];
                 const T a = (T)wd.x, b = (T)wd.y, g = (T)wd.z, d = (T)wd.w;
                 const T *src = wrow;
                 if (NPASS == 2) {
                     // first half drift (table 1) at positions i0 + m - 4 + q,
                     // q in [0, TW + 9), m the offset of the second
-                    const int m = dm2[j];
-                    const double4 w1 = dw1[j];
                     if (t < NRUN1) {
                         T o[V];
                         spline_run<T, V>(src, t, (T)w1.x, (T)w1.y, (T)w1.z, (T)w1.w, o);
