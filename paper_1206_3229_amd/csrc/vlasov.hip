@@ -219,7 +219,7 @@ int density_force(vlasov_ctx *c)
     const int nx = (int)P.nx;
     double *rho = c->at<double>(c->L.rho);
     double *F = c->at<double>(c->L.F);
-    launch(c, VLASOV_K_DENSITY, vk::k_density, dim3((unsigned)((nx + 15) / 16)), dim3(256),
+    launch(c, VLASOV_K_DENSITY, vk::k_density, dim3((unsigned)((nx + 15) / 16)), dim3(1024),
            c->at<double>(c->L.part), rho, nx, (int)c->nblk, c->dp);
     int rc = check_launch("density");
     if (rc) return rc;

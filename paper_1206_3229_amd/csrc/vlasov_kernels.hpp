@@ -925,17 +925,73 @@ __device__ __forceinline__ void density_block(const double *__restrict__ part, d
     if (g == 0 && i < nx) rho[i] = dp * S[0][c];
 }
 
-static __global__ __launch_bounds__(256) void k_density(const double *__restrict__ part, double *__restrict__ rho, int nx,
-                                                 int nblk, double dp)
+// Marks loaded values as used here, after all of their loads, so that the
+// compiler issues the loads together before any branch that follows (a load
+// whose only use is conditional is otherwise moved into the branch, next to
+// a wait for it).
+template <typename T> __device__ __forceinline__ void keep_issued(T &v) { asm volatile("" : "+v"(v)); }
+
+// The same sums with 1024 threads: thread (c, g) forms the serial sum of
+// block class g alone, its loads (blocks g, g + 64, g + 128, g + 192 of a
+// round) all in flight at once.
+static __global__ __launch_bounds__(1024) void k_density(const double *__restrict__ part, double *__restrict__ rho,
+                                                  int nx, int nblk, double dp)
 {
     __shared__ double S[64][17];
-    density_block(part, rho, nx, nblk, dp, blockIdx.x, S);
+    const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const int i = blockIdx.x * 16 + c;
+    const int ic = min(i, nx - 1);
+    double acc = 0.0;
+    for (int b0 = 0; b0 < nblk; b0 += 256) {
+        double x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            x[k] = part[(size_t)min(b0 + g + 64 * k, nblk - 1) * nx + ic];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) keep_issued(x[k]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (b0 + g + 64 * k < nblk) acc = acc + x[k];
+    }
+    S[g][c] = acc;
+    __syncthreads();
+    for (int d = 32; d >= 1; d >>= 1) {
+        if (g < d) S[g][c] = S[g][c] + S[g + d][c];
+        __syncthreads();
+    }
+    if (g == 0 && i < nx) rho[i] = dp * S[0][c];
 }
 
-// Stage n doubles into LDS (whole workgroup).
-__device__ __forceinline__ void stage(double *dst, const double *__restrict__ src, int n)
+// Stage three arrays of n doubles into LDS (whole workgroup), the twelve
+// loads of a round per thread in flight before their LDS writes.
+__device__ __forceinline__ void stage3(double *d0, const double *__restrict__ s0, double *d1,
+                                       const double *__restrict__ s1, double *d2, const double *__restrict__ s2, int n)
 {
-    for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
+    const int bd = blockDim.x;
+    for (int k0 = threadIdx.x; k0 < n; k0 += 4 * bd) {
+        double v[3][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = min(k0 + u * bd, n - 1);
+            v[0][u] = s0[k];
+            v[1][u] = s1[k];
+            v[2][u] = s2[k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            keep_issued(v[0][u]);
+            keep_issued(v[1][u]);
+            keep_issued(v[2][u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (k0 + u * bd < n) {
+                d0[k0 + u * bd] = v[0][u];
+                d1[k0 + u * bd] = v[1][u];
+                d2[k0 + u * bd] = v[2][u];
+            }
+    }
 }
 
 // Magnetization of eq. (mxmydef) by one wavefront from LDS copies of rho, cos
@@ -982,9 +1038,7 @@ __device__ __forceinline__ void force_hmf_block(const double *__restrict__ rho, 
 {
     const double *r = rho, *c = cs, *s = sn;
     if (STAGED) {
-        stage(L, rho, n);
-        stage(L + FORCE_LDS_MAX, cs, n);
-        stage(L + 2 * FORCE_LDS_MAX, sn, n);
+        stage3(L, rho, L + FORCE_LDS_MAX, cs, L + 2 * FORCE_LDS_MAX, sn, n);
         __syncthreads();
         r = L;
         c = L + FORCE_LDS_MAX;
@@ -1023,9 +1077,7 @@ __device__ __forceinline__ void magnetization_block(const double *__restrict__ r
 {
     const double *r = rho, *c = cs, *s = sn;
     if (STAGED) {
-        stage(L, rho, n);
-        stage(L + FORCE_LDS_MAX, cs, n);
-        stage(L + 2 * FORCE_LDS_MAX, sn, n);
+        stage3(L, rho, L + FORCE_LDS_MAX, cs, L + 2 * FORCE_LDS_MAX, sn, n);
         __syncthreads();
         r = L;
         c = L + FORCE_LDS_MAX;
@@ -1088,7 +1140,19 @@ __device__ __forceinline__ void force_sheet_block(const double *__restrict__ rho
 {
     const int c = (n + 63) / 64;
     if (STAGED) {
-        for (int i = threadIdx.x; i < n; i += blockDim.x) L[(i % c) * 65 + i / c] = rho[i];
+        const int bd = blockDim.x;
+        for (int i0 = threadIdx.x; i0 < n; i0 += 4 * bd) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = rho[min(i0 + u * bd, n - 1)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) keep_issued(v[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + u * bd;
+                if (i < n) L[(i % c) * 65 + i / c] = v[u];
+            }
+        }
         __syncthreads();
     }
     if (threadIdx.x < 64) {
