@@ -74,7 +74,7 @@ Layout layout_of(const vlasov_params &p)
     L.mom_out = take(10 * sizeof(double));
     L.mom_col = take(6 * nx * sizeof(double));
     L.mom_phi = take(nx * sizeof(double));
-    L.gs_g = take((vk::GS_K + 1) * sizeof(double));
+    L.gs_g = take(2 * sizeof(double));
     L.total = o;
     return L;
 }
@@ -627,17 +627,11 @@ int vlasov_init(const vlasov_params *p, const double *f0_host, void *f_dev, void
             V[s] = Vd((double)e * c->dx);
         }
     }
-    // Green's function of the (1, 4, 1) operator of eq. (tridiagsys), times 6:
-    // g_k = sqrt(3) r^k, r = sqrt(3) - 2 (powers by repeated multiplication)
-    std::vector<double> gs(vk::GS_K + 1);
-    {
-        const double r = sqrt(3.0) - 2.0;
-        double gk = sqrt(3.0);
-        for (int k = 0; k <= vk::GS_K; ++k) {
-            gs[k] = gk;
-            gk *= r;
-        }
-    }
+    // Recursion coefficients of the (1, 4, 1) operator of eq. (tridiagsys):
+    // its root r = sqrt(3) - 2 and the factor -6 r of D
+    std::vector<double> gs(2);
+    gs[0] = sqrt(3.0) - 2.0;
+    gs[1] = -6.0 * gs[0];
     const size_t nxb = (size_t)p->nx * sizeof(double);
     auto cleanup_fail = [&](int rc) {
         delete c;

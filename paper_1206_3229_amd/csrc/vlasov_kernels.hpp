@@ -36,6 +36,12 @@ template <> struct FD<float> {
 __device__ __forceinline__ double vfma(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ float vfma(float a, float b, float c) { return fmaf(a, b, c); }
 
+// Marks loaded values as used here, after all of their loads, so that the
+// compiler issues the loads together before any branch that follows (a load
+// whose only use is conditional is otherwise moved into the branch, next to
+// a wait for it).
+template <typename T> __device__ __forceinline__ void keep_issued(T &v) { __asm__ __volatile__("" : "+v"(v)); }
+
 // x points at the centre sample; reads x[-4..4].  Symmetric pairs first,
 // accumulated from the outermost pair inwards.
 template <typename T>
@@ -748,70 +754,96 @@ static __global__ __launch_bounds__(NT) void k_kick_drift(const T *__restrict__ 
 // Eq. (tridiagsys): the global spline, the paper's baseline for the local f''.
 // D_i = f''_i du^2 solves D_{i-1} + 4 D_i + D_{i+1} = 6 S_i with S_i =
 // f_{i+1} - 2 f_i + f_{i-1} (on a periodic line, or on the line continued by
-// zeros).  Its solution is the convolution of 6 S with the Green's function of
-// the (1, 4, 1) operator, r^|k| / sqrt(12), r = sqrt(3) - 2: D_i = sum_k g_|k|
-// S_{i+k} with g_k = sqrt(3) r^k, truncated at |k| <= GS_K where |r|^GS_K is
-// below FP64 resolution.  On a periodic line the sum wraps around the line
-// (the periodic inverse is the wrapped infinite one).  One workgroup of 256
-// threads moves one line of n <= GS_MAX_N samples through LDS: the samples,
-// S and D (all with GS_E cells beyond each end), then the spline of eq.
-// (splinegen) at the feet.  Lines are the rows of f (the drift) or of its
-// transpose (the kick, shift from the force of the column).
+// zeros).  The (1, 4, 1) operator factors as -(1/r)(1 - r E)(1 - r E^-1),
+// E the shift to the next node and r = sqrt(3) - 2 its root inside the unit
+// circle, so D = -6 r x with y_i = S_i + r y_{i-1} (causal) and x_i = y_i +
+// r x_{i+1} (anticausal): the convolution of S with sqrt(3) r^|k|.  Each
+// thread runs both recursions over a chunk of GS_CH nodes, started GS_K nodes
+// outside its chunk from 0 (|r|^GS_K is below FP64 resolution), so the
+// chunks need no sequential pass.  On a periodic line the recursions wrap;
+// with zero extension they run over the line continued by GS_E zeros at each
+// end, where D decays by |r| per cell (farther feet read D = 0).  One
+// workgroup of 256 threads moves one line of n <= GS_MAX_N samples through
+// LDS (the samples, and S, y and D in turn in a second array), then
+// evaluates the spline of eq. (splinegen) at the feet.  Lines are the rows
+// of f (the drift) or of its transpose (the kick, shift from the force of
+// the column).
 // ---------------------------------------------------------------------------
 constexpr int GS_K = 30, GS_E = GS_K + 2, GS_MAX_N = 4096, GS_NT = 256;
 constexpr int GS_LDS = GS_MAX_N + 2 * GS_E;
+constexpr int GS_CH = (GS_LDS + GS_NT - 1) / GS_NT;  // nodes per thread
 
 template <typename T, int BC, bool KICK>
 static __global__ __launch_bounds__(GS_NT) void k_gs_line(const T *__restrict__ fin, T *__restrict__ fout, int n,
                                                    const int32_t *__restrict__ dm,
                                                    const double4 *__restrict__ dw,
                                                    const double *__restrict__ F, double dt, double dh,
-                                                   const double *__restrict__ gtab)
+                                                   const double *__restrict__ gcoef)
 {
-    __shared__ T fe[GS_LDS], S[GS_LDS], D[GS_LDS];
-    __shared__ T g[GS_K + 1];
+    __shared__ T fe[GS_LDS], Q[GS_LDS];
     const int line = blockIdx.x, t = threadIdx.x;
     const T *src = fin + (size_t)line * n;
-    const int ne = n + 2 * GS_E;  // extended index e = i + GS_E, i in [-GS_E, n + GS_E)
-    for (int k = t; k <= GS_K; k += GS_NT) g[k] = (T)gtab[k];
-    for (int e = t; e < ne; e += GS_NT) {
-        const int i = e - GS_E;
-        if (BC == BC_PERIODIC) {
-            // lines shorter than the extension wrap more than once
-            int q = i < 0 ? i + n : (i >= n ? i - n : i);
-            q = q < 0 ? wrap(q, n) : (q >= n ? wrap(q, n) : q);
-            fe[e] = src[q];
-        } else {
-            fe[e] = (i >= 0 && i < n) ? src[i] : T(0);
+    const T r = (T)gcoef[0], cD = (T)gcoef[1];
+    // working line: the n nodes (periodic, indices mod n) or the extended
+    // line e = i + GS_E, i in [-GS_E, n + GS_E) (zero extension)
+    const int N = BC == BC_PERIODIC ? n : n + 2 * GS_E;
+    for (int e0 = t; e0 < N; e0 += 4 * GS_NT) {
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = BC == BC_PERIODIC ? e0 + u * GS_NT : e0 + u * GS_NT - GS_E;
+            v[u] = src[min(max(i, 0), n - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) keep_issued(v[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * GS_NT;
+            const int i = BC == BC_PERIODIC ? e : e - GS_E;
+            if (e < N) fe[e] = (i >= 0 && i < n) ? v[u] : T(0);
         }
     }
     __syncthreads();
-    for (int e = t; e < ne; e += GS_NT)
-        S[e] = (e == 0 || e == ne - 1) ? T(0) : (fe[e - 1] + fe[e + 1]) - T(2) * fe[e];
+    auto at = [&](const T *a, int e) -> T {  // a[e] under the boundary rule of the working line
+        if (BC == BC_PERIODIC) return a[e >= 0 && e < n ? e : wrap(e, n)];
+        return (e >= 0 && e < N) ? a[e] : T(0);
+    };
+    for (int e = t; e < N; e += GS_NT)
+        Q[e] = (BC != BC_PERIODIC && (e == 0 || e == N - 1)) ? T(0)
+                                                             : (at(fe, e - 1) + at(fe, e + 1)) - T(2) * fe[e];
     __syncthreads();
-    // D of the nodes of the line (periodic), or of every node of the
-    // extension [-GS_E + 1, n + GS_E - 1) (zero extension: D decays by |r|
-    // per cell away from the line, so farther feet read 0)
-    const int e0 = BC == BC_PERIODIC ? GS_E : 1, e1 = BC == BC_PERIODIC ? n + GS_E : ne - 1;
-    for (int e = e0 + t; e < e1; e += GS_NT) {
-        T acc;
-        if (BC == BC_PERIODIC) {
-            auto Sw = [&](int q) {  // periodic S of node q - GS_E
-                int i = q - GS_E;
-                i = i < 0 ? i + n : (i >= n ? i - n : i);
-                i = i < 0 ? wrap(i, n) : (i >= n ? wrap(i, n) : i);
-                return S[i + GS_E];
-            };
-            acc = g[GS_K] * (Sw(e - GS_K) + Sw(e + GS_K));
-            for (int k = GS_K - 1; k >= 1; --k) acc = vfma(g[k], Sw(e - k) + Sw(e + k), acc);
-            D[e] = vfma(g[0], Sw(e), acc);
-        } else {
-            auto Sz = [&](int q) { return (q >= 1 && q < ne - 1) ? S[q] : T(0); };
-            acc = g[GS_K] * (Sz(e - GS_K) + Sz(e + GS_K));
-            for (int k = GS_K - 1; k >= 1; --k) acc = vfma(g[k], Sz(e - k) + Sz(e + k), acc);
-            D[e] = vfma(g[0], Sz(e), acc);
+    const int c0 = t * GS_CH;  // this thread's chunk [c0, c0 + GS_CH)
+    const bool mine = c0 < N;
+    T w[GS_CH];
+    if (mine) {  // causal recursion y_e = S_e + r y_{e-1}
+        T acc = T(0);
+        for (int k = GS_K; k >= 1; --k) acc = vfma(r, acc, at(Q, c0 - k));
+#pragma unroll
+        for (int u = 0; u < GS_CH; ++u) {
+            acc = vfma(r, acc, at(Q, c0 + u));
+            w[u] = acc;
         }
     }
+    __syncthreads();
+    if (mine)
+#pragma unroll
+        for (int u = 0; u < GS_CH; ++u)
+            if (c0 + u < N) Q[c0 + u] = w[u];
+    __syncthreads();
+    if (mine) {  // anticausal recursion x_e = y_e + r x_{e+1}, D = -6 r x
+        T acc = T(0);
+        for (int k = GS_K + GS_CH - 1; k >= GS_CH; --k) acc = vfma(r, acc, at(Q, c0 + k));
+#pragma unroll
+        for (int u = GS_CH - 1; u >= 0; --u) {
+            acc = vfma(r, acc, at(Q, c0 + u));
+            w[u] = cD * acc;
+        }
+    }
+    __syncthreads();
+    if (mine)
+#pragma unroll
+        for (int u = 0; u < GS_CH; ++u)
+            if (c0 + u < N) Q[c0 + u] = w[u];
     __syncthreads();
     // foot of the line's shift
     int m;
@@ -825,11 +857,11 @@ static __global__ __launch_bounds__(GS_NT) void k_gs_line(const T *__restrict__ 
         d = (T)ft.d;
     } else {
         m = dm[line];
-        const double4 w = dw[line];
-        a = (T)w.x;
-        b = (T)w.y;
-        gg = (T)w.z;
-        d = (T)w.w;
+        const double4 wv = dw[line];
+        a = (T)wv.x;
+        b = (T)wv.y;
+        gg = (T)wv.z;
+        d = (T)wv.w;
     }
     T *dst = fout + (size_t)line * n;
     for (int i = t; i < n; i += GS_NT) {
@@ -837,15 +869,15 @@ static __global__ __launch_bounds__(GS_NT) void k_gs_line(const T *__restrict__ 
         T fk, fk1, Dk, Dk1;
         if (BC == BC_PERIODIC) {
             const int q = k >= n ? k - n : k, q1 = q + 1 == n ? 0 : q + 1;  // m in [0, n)
-            fk = fe[q + GS_E];
-            fk1 = fe[q1 + GS_E];
-            Dk = D[q + GS_E];
-            Dk1 = D[q1 + GS_E];
+            fk = fe[q];
+            fk1 = fe[q1];
+            Dk = Q[q];
+            Dk1 = Q[q1];
         } else {
             fk = (k >= 0 && k < n) ? fe[k + GS_E] : T(0);
             fk1 = (k + 1 >= 0 && k + 1 < n) ? fe[k + 1 + GS_E] : T(0);
-            Dk = (k > -GS_E && k < n + GS_E - 1) ? D[k + GS_E] : T(0);
-            Dk1 = (k + 1 > -GS_E && k + 1 < n + GS_E - 1) ? D[k + 1 + GS_E] : T(0);
+            Dk = (k > -GS_E && k < n + GS_E - 1) ? Q[k + GS_E] : T(0);
+            Dk1 = (k + 1 > -GS_E && k + 1 < n + GS_E - 1) ? Q[k + 1 + GS_E] : T(0);
         }
         dst[i] = spline(a, b, gg, d, fk, fk1, Dk, Dk1);
     }
@@ -925,11 +957,6 @@ __device__ __forceinline__ void density_block(const double *__restrict__ part, d
     if (g == 0 && i < nx) rho[i] = dp * S[0][c];
 }
 
-// Marks loaded values as used here, after all of their loads, so that the
-// compiler issues the loads together before any branch that follows (a load
-// whose only use is conditional is otherwise moved into the branch, next to
-// a wait for it).
-template <typename T> __device__ __forceinline__ void keep_issued(T &v) { asm volatile("" : "+v"(v)); }
 
 // The same sums with 1024 threads: thread (c, g) forms the serial sum of
 // block class g alone, its loads (blocks g, g + 64, g + 128, g + 192 of a
