@@ -317,7 +317,7 @@ enum {
     VLASOV_K_KICK = 4,     /* momentum advection */
     VLASOV_K_MOMENTS = 5,  /* diagnostics */
     VLASOV_K_KICK_DRIFT2 = 6,  /* kick fused with two half drifts + density partial sums */
-    VLASOV_K_FILTER = 7,   /* the filter along p */
+    VLASOV_K_FILTER = 7,   /* the filter along p (fused with the kick of a filtered step) */
     VLASOV_K_COUNT = 8
 };
 

@@ -319,6 +319,38 @@ int filter(vlasov_ctx *c)
     return c->P.storage == VLASOV_F32 ? launch_filter<float>(c) : launch_filter<double>(c);
 }
 
+// Kick of step size h and the filter in one pass (local spline).
+template <typename T>
+int launch_kick_filter(vlasov_ctx *c, double h)
+{
+    const vlasov_params &P = c->P;
+    const int ntx = (int)((P.nx + 255) / 256), nty = (int)((P.np + FILTER_R - 1) / FILTER_R);
+    const dim3 grid((unsigned)vk::xcd_grid(ntx, nty));
+    const T *fin = (const T *)c->fcur();
+    T *fout = (T *)c->fnext();
+    const double cf = P.filter_strength / 256.0;
+    if (P.bc_p == VLASOV_BC_PERIODIC)
+        launch(c, VLASOV_K_FILTER, vk::k_kick_filter<T, vk::BC_PERIODIC, FILTER_R>, grid, dim3(256), fin, fout,
+               force_ptr(c), h, c->dp, cf, (int)P.nx, (int)P.np, ntx, nty);
+    else
+        launch(c, VLASOV_K_FILTER, vk::k_kick_filter<T, vk::BC_ZERO, FILTER_R>, grid, dim3(256), fin, fout,
+               force_ptr(c), h, c->dp, cf, (int)P.nx, (int)P.np, ntx, nty);
+    int rc = check_launch("kick and filter");
+    if (rc == VLASOV_OK) c->cur ^= 1;
+    return rc;
+}
+
+// The kick followed by the filter: one pass with the local spline, the
+// transposed kick and then the filter with the global spline.
+int kick_filter(vlasov_ctx *c, double h)
+{
+    if (c->P.spline == VLASOV_SPLINE_GS) {
+        int rc = kick(c, h);
+        return rc == VLASOV_OK ? filter(c) : rc;
+    }
+    return c->P.storage == VLASOV_F32 ? launch_kick_filter<float>(c, h) : launch_kick_filter<double>(c, h);
+}
+
 // ---------------------------------------------------------------------------
 // Global spline (eq. tridiagsys): one workgroup per line; the kick runs on the
 // rows of the transpose.
@@ -443,8 +475,7 @@ int kick_then_drift(vlasov_ctx *c, int k, int tb, double h, bool filt)
         if (w == 256) return f32 ? launch_kick_drift_w<float, 256>(c, k, h) : launch_kick_drift_w<double, 256>(c, k, h);
         return f32 ? launch_kick_drift_w<float, 512>(c, k, h) : launch_kick_drift_w<double, 512>(c, k, h);
     }
-    int rc = kick(c, h);
-    if (rc == VLASOV_OK && filt) rc = filter(c);
+    int rc = filt ? kick_filter(c, h) : kick(c, h);
     if (rc == VLASOV_OK) rc = drift(c, k, tb, tb >= 0);
     return rc;
 }

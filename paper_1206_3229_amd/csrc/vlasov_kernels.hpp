@@ -498,6 +498,56 @@ static __global__ __launch_bounds__(256) void k_filter_p(const T *__restrict__ f
     }
 }
 
+// The kick of a filtered step followed by the filter, in one pass: each
+// thread kicks rows j0 - 4 .. j0 + R + 3 of its column (the filter's window;
+// rows outside the grid are zero with zero extension, wrapped otherwise)
+// from R + 18 samples held in registers, then filters rows j0 .. j0 + R - 1.
+// Every value is computed as by k_kick and k_filter_p, so the result is the
+// same bit for bit.
+// ---------------------------------------------------------------------------
+template <typename T, int BC, int R>
+static __global__ __launch_bounds__(256) void k_kick_filter(const T *__restrict__ fin, T *__restrict__ fout,
+                                                     const double *__restrict__ F, double dt, double dp, double c,
+                                                     int nx, int np, int ntx, int nty)
+{
+    int tx, ty;
+    if (!xcd_tile(ntx, nty, tx, ty)) return;
+    const int i = tx * 256 + threadIdx.x;
+    if (i >= nx) return;
+    const int j0 = ty * R;
+    const Foot ft = foot_of_shift((F[i] * dt) / dp);
+    const int m = reduce_offset(ft.m, np, BC);
+    const T a = (T)ft.a, b = (T)ft.b, g = (T)ft.g, d = (T)ft.d;
+    const int base = j0 - 8 + m;  // sample 0: row j0 - 4 + m - 4
+    const T *col = fin + i;
+    T w[R + 18];
+#pragma unroll
+    for (int s = 0; s < R + 18; ++s) w[s] = sample<T, BC>(col, base + s, np, (size_t)nx);
+    // kicked rows j0 - 4 + u, u in [0, R + 8)
+    T k[R + 8];
+    T Dk = second_diff(w + 4);
+#pragma unroll
+    for (int u = 0; u < R + 8; ++u) {
+        const T Dk1 = second_diff(w + u + 5);
+        const T y = spline(a, b, g, d, w[u + 4], w[u + 5], Dk, Dk1);
+        Dk = Dk1;
+        const int row = j0 - 4 + u;
+        k[u] = (BC == BC_PERIODIC || (row >= 0 && row < np)) ? y : T(0);
+    }
+    const T cc = (T)c;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const T *q = k + r + 4;
+        T sm = q[-4] + q[4];
+        sm = vfma(T(-8), q[-3] + q[3], sm);
+        sm = vfma(T(28), q[-2] + q[2], sm);
+        sm = vfma(T(-56), q[-1] + q[1], sm);
+        sm = vfma(T(70), q[0], sm);
+        const int j = j0 + r;
+        if (j < np) fout[(size_t)j * nx + i] = vfma(-cc, sm, q[0]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Step 3 fused with the drift that follows it (step 4, and with NPASS = 2 also
 // step 1 of the next step).  Once the force is known nothing global separates
