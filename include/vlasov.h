@@ -12,7 +12,10 @@
  * the drifted f (eq. step2), full kick in p, half drift in x.  Every sweep
  * evaluates the cubic spline of eqs. (splinegen, splinecoeffs) at the foot of
  * the characteristic with second derivatives from the eighth-order stencil of
- * eq. (findif).
+ * eq. (findif).  Options of vlasov_params: the global spline of eq.
+ * (tridiagsys) in place of the stencil (the paper's comparison baseline), and
+ * the fourth-order compositions of the step and the filter in p that the
+ * conclusions name as extensions.
  *
  * Conventions for every call:
  *   - Status: 0 (VLASOV_OK) on success, VLASOV_PENDING (1) from poll only,
@@ -94,7 +97,8 @@ typedef struct {
     double dt;        /* time step, finite and nonzero */
     double ring_eps;  /* softening of eq. (ringpot), > 0 (ring only) */
     double sheet_G;   /* coupling of the sheet model, F = 2 pi G (M(>x) - M(<x)) */
-    int64_t hist_cap; /* entries kept of the per-step magnetization history (>= 0) */
+    int64_t hist_cap; /* entries kept of the magnetization history, one per force
+                         evaluation (>= 0) */
     int32_t spline;   /* VLASOV_SPLINE_FD: f'' by the local stencil of eq. (findif);
                          VLASOV_SPLINE_GS: the global spline of eq. (tridiagsys), the
                          paper's baseline (lines of at most 4096 samples, single contexts
@@ -116,9 +120,10 @@ typedef struct {
  * (mx, my) the magnetization of eq. (mxmydef) (HMF and ring; 0 otherwise),
  * l2 = int f^2 and entropy = -int f log f over the points where f > 0 (Casimirs
  * of eq. casimirs), neg_mass = int f over the points where f < 0 (the spline
- * overshoot).  Every quantity but the entropy is computed in the same order
- * as the reference and bit for bit the same; the entropy uses the device's
- * log and agrees to a relative 1e-12. */
+ * overshoot).  Every quantity but the entropy is computed in a fixed order of
+ * summation (64 interleaved partial sums per line, then a pairwise tree; column
+ * sums over 16-row blocks first), independent of the launch shape, so results
+ * repeat bit for bit; the entropy uses the device's log. */
 typedef struct {
     double mass, momentum, kinetic, potential, energy, mx, my, l2, entropy, neg_mass;
 } vlasov_moments_t;
