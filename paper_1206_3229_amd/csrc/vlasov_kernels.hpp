@@ -837,25 +837,35 @@ static __global__ __launch_bounds__(GS_NT) void k_gs_line(const T *__restrict__ 
     // working line: the n nodes (periodic, indices mod n) or the extended
     // line e = i + GS_E, i in [-GS_E, n + GS_E) (zero extension)
     const int N = BC == BC_PERIODIC ? n : n + 2 * GS_E;
-    for (int e0 = t; e0 < N; e0 += 4 * GS_NT) {
-        T v[4];
+    {
+        // all GS_CH loads of a thread in flight at once
+        T v[GS_CH];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = BC == BC_PERIODIC ? e0 + u * GS_NT : e0 + u * GS_NT - GS_E;
+        for (int u = 0; u < GS_CH; ++u) {
+            const int e = t + u * GS_NT;
+            const int i = BC == BC_PERIODIC ? e : e - GS_E;
             v[u] = src[min(max(i, 0), n - 1)];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) keep_issued(v[u]);
+        for (int u = 0; u < GS_CH; ++u) keep_issued(v[u]);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = e0 + u * GS_NT;
+        for (int u = 0; u < GS_CH; ++u) {
+            const int e = t + u * GS_NT;
             const int i = BC == BC_PERIODIC ? e : e - GS_E;
             if (e < N) fe[e] = (i >= 0 && i < n) ? v[u] : T(0);
         }
     }
     __syncthreads();
-    auto at = [&](const T *a, int e) -> T {  // a[e] under the boundary rule of the working line
-        if (BC == BC_PERIODIC) return a[e >= 0 && e < n ? e : wrap(e, n)];
+    // a[e] under the boundary rule of the working line; e lies in
+    // [-GS_K, N + GS_K + GS_CH), so two conditional steps wrap it once the
+    // line is longer than that excursion (shorter lines take the division)
+    const bool short_line = n < GS_K + GS_CH + 1;
+    auto at = [&](const T *a, int e) -> T {
+        if (BC == BC_PERIODIC) {
+            if (short_line) return a[wrap(e, n)];
+            const int q = e < 0 ? e + n : e;
+            return a[q >= n ? q - n : q];
+        }
         return (e >= 0 && e < N) ? a[e] : T(0);
     };
     for (int e = t; e < N; e += GS_NT)
