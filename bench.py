@@ -297,8 +297,8 @@ def main():
                          "(no autotuning)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is described in DESIGN.md but not built)", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(a simulation is not sharded across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import torch
