@@ -568,6 +568,9 @@ static __global__ __launch_bounds__(256) void k_kick_filter(const T *__restrict_
 // carried across the blocks of the tile, and writes the kicked row into the
 // LDS window of the drift at kappa - krel_j.  The taller the tile, the
 // smaller the share of the 10 halo rows the kick reads above and below it.
+// The rows are software-pipelined with one barrier per row: the kick of row
+// r, the first half drift of row r - 1 and the second of row r - 2 run
+// between two barriers, on two window and two intermediate row buffers.
 // ---------------------------------------------------------------------------
 constexpr int KD_SPR = 8;
 
@@ -607,7 +610,10 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
         win1[s] = T(0);
     }
     if (NPASS == 2)
-        for (int s = MIDN + t; s < LDM; s += NT) mid[s] = T(0);
+        for (int s = MIDN + t; s < LDM; s += NT) {
+            mid[s] = T(0);
+            mid[LDM + s] = T(0);
+        }
 
     // Kicked columns of this thread: foot of the p shift (eq. step3), first
     // sample row, and masks of the samples that lie inside the grid.
@@ -683,18 +689,18 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
         double acc[V];
 #pragma unroll
         for (int k = 0; k < V; ++k) acc[k] = 0.0;
+        // Three stages in flight, one barrier per row: the kick of row r, the
+        // first half drift of row r - 1 and the second of row r - 2 (for
+        // NPASS = 1: the kick of row r and the half drift of row r - 1).
+        // Rows alternate between two window and two intermediate buffers.
+        constexpr int LAG = NPASS == 2 ? 2 : 1;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (FULL || R * blk + r < nr) {
+        for (int r = 0; r < R + LAG; ++r) {
+            if (r < R && (FULL || R * blk + r < nr)) {
                 const int j = jb + r;
                 T *wrow = (r & 1) ? win1 : win0;
                 settle(r + 9);
                 const int rel = krel[j];
-                // the row's drift tables, requested before the kick so that
-                // their latency hides behind it
-                const double4 wd = (NPASS == 2 ? dw2 : dw1)[j];
-                const double4 w1 = NPASS == 2 && dw1 != dw2 ? dw1[j] : wd;  // one table: Strang
-                const int m = NPASS == 2 ? dm2[j] : 0;
 #pragma unroll
                 for (int k = 0; k < KC; ++k) {
                     const T Dk1 = second_diff(w[k] + r + 5);
@@ -707,35 +713,40 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
                 // the samples of the next block are requested too (clamped
                 // or wrapped addresses; unused after the last block)
                 if (r + 10 + PF < NS && (RB > 1 || r + 10 + PF < R + 10)) request(r + 10 + PF);
-                __syncthreads();
-                const T a = (T)wd.x, b = (T)wd.y, g = (T)wd.z, d = (T)wd.w;
-                const T *src = wrow;
-                if (NPASS == 2) {
-                    // first half drift (table 1) at positions i0 + m - 4 + q,
-                    // q in [0, TW + 9), m the offset of the second
-                    if (t < NRUN1) {
-                        T o[V];
-                        spline_run<T, V>(src, t, (T)w1.x, (T)w1.y, (T)w1.z, (T)w1.w, o);
-                        if (BCX == BC_ZERO) {
-                            const int q = i0 + m - 4 + V * t;
+            }
+            if (NPASS == 2 && r >= 1 && r - 1 < R && (FULL || R * blk + r - 1 < nr)) {
+                // first half drift (table 1) at positions i0 + m - 4 + q,
+                // q in [0, TW + 9), m the offset of the second
+                const int q1 = r - 1, j = jb + q1;
+                const T *src = (q1 & 1) ? win1 : win0;
+                T *mrow = mid + ((q1 & 1) ? LDM : 0);
+                const double4 w1 = dw1[j];
+                const int m = dm2[j];
+                if (t < NRUN1) {
+                    T o[V];
+                    spline_run<T, V>(src, t, (T)w1.x, (T)w1.y, (T)w1.z, (T)w1.w, o);
+                    if (BCX == BC_ZERO) {
+                        const int q = i0 + m - 4 + V * t;
 #pragma unroll
-                            for (int k = 0; k < V; ++k)
-                                if (q + k < 0 || q + k >= nx) o[k] = T(0);
-                        }
-#pragma unroll
-                        for (int k = 0; k < V; k += 2) {
-                            typename Vec2<T>::type ww;
-                            ww.x = o[k];
-                            ww.y = o[k + 1];
-                            reinterpret_cast<typename Vec2<T>::type *>(mid + V * t)[k / 2] = ww;
-                        }
+                        for (int k = 0; k < V; ++k)
+                            if (q + k < 0 || q + k >= nx) o[k] = T(0);
                     }
-                    __syncthreads();
-                    src = mid;
+#pragma unroll
+                    for (int k = 0; k < V; k += 2) {
+                        typename Vec2<T>::type ww;
+                        ww.x = o[k];
+                        ww.y = o[k + 1];
+                        reinterpret_cast<typename Vec2<T>::type *>(mrow + V * t)[k / 2] = ww;
+                    }
                 }
+            }
+            if (r >= LAG && (FULL || R * blk + r - LAG < nr)) {
+                const int q2 = r - LAG, j = jb + q2;
+                const T *src = NPASS == 2 ? mid + ((q2 & 1) ? LDM : 0) : ((q2 & 1) ? win1 : win0);
+                const double4 wd = (NPASS == 2 ? dw2 : dw1)[j];
                 if (own) {
                     T o[V];
-                    spline_run<T, V>(src, t, a, b, g, d, o);
+                    spline_run<T, V>(src, t, (T)wd.x, (T)wd.y, (T)wd.z, (T)wd.w, o);
                     if (FULL) {
 #pragma unroll
                         for (int k = 0; k < V; k += 2) {
@@ -753,6 +764,7 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
                     }
                 }
             }
+            __syncthreads();
         }
         if (PARTIALS && own) {
             double *prow = part + (size_t)(ty * RB + blk) * nx;
@@ -774,9 +786,11 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
     }
 }
 
+// FP32: six waves per SIMD (at most 80 VGPRs) measured faster than the
+// compiler's own five, despite a few spilled registers.
 template <typename T, int NPASS, int BCX, int BCP, bool PARTIALS, int NT, int TW, int PF, int RB, int VR = 2,
           int UB = 1>
-static __global__ __launch_bounds__(NT) void k_kick_drift(const T *__restrict__ fin, T *__restrict__ fout,
+static __global__ __launch_bounds__(NT, sizeof(T) == 8 ? 4 : 6) void k_kick_drift(const T *__restrict__ fin, T *__restrict__ fout,
                                                    const double *__restrict__ F, double dt, double dp,
                                                    const int32_t *__restrict__ dm1,
                                                    const double4 *__restrict__ dw1,
@@ -788,7 +802,7 @@ static __global__ __launch_bounds__(NT) void k_kick_drift(const T *__restrict__ 
 {
     using G = typename KickDriftGeom<NPASS, NT, TW, VR>::G;
     __shared__ __attribute__((aligned(16))) T win[2][G::LDA];
-    __shared__ __attribute__((aligned(16))) T mid[G::LDM];
+    __shared__ __attribute__((aligned(16))) T mid[2 * G::LDM];  // two intermediate rows
     int tx, ty;
     if (!xcd_tile(ntx, nty, tx, ty)) return;
     const bool full = (ty + 1) * (ROWS_PER_BLOCK * RB) <= np && (tx + 1) * TW <= nx && (nx & 1) == 0;
