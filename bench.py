@@ -316,7 +316,7 @@ def main():
             return None, None
         from paper_1206_3229_amd import autotune
         pw, fw, _ = WORKLOADS[workload]()
-        best = autotune.tune(pw, fw, use_cache=False)
+        best = autotune.tune(pw, fw, use_cache=False, tie=0.03)
         return (best["drift_threads"], best["kick_rows"], best["kick_drift_width"], best["kick_drift_blocks"]), best
 
     shape, tuned = pick_shape(args.workload)

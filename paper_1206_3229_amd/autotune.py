@@ -49,9 +49,12 @@ def _store(key: str, entry: dict):
         pass
 
 
-def tune(params, f0: np.ndarray, steps: int = 10, reps: int = 3, use_cache: bool = True) -> dict:
+def tune(params, f0: np.ndarray, steps: int = 10, reps: int = 3, use_cache: bool = True, tie: float = 0.0) -> dict:
     """Best launch shape for this grid:
-    {"drift_threads", "kick_rows", "kick_drift_width", "kick_drift_blocks", "us_per_step", "table"}."""
+    {"drift_threads", "kick_rows", "kick_drift_width", "kick_drift_blocks", "us_per_step", "table"}.
+    With tie > 0 the first candidate (in the library's order) within a
+    factor 1 + tie of the fastest is taken, so that shapes whose times differ
+    by noise give a repeatable choice."""
     import torch
     arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName
     key = _key(arch, params)
@@ -74,9 +77,11 @@ def tune(params, f0: np.ndarray, steps: int = 10, reps: int = 3, use_cache: bool
             times.append(e0.elapsed_time(e1) * 1e3 / steps)
         table.append((float(np.median(times)), nt, kr, kw, kb))
     s.close()
+    fastest = min(t[0] for t in table)
+    pick = next(t for t in table if t[0] <= (1.0 + tie) * fastest)
     table.sort()
-    best = {"drift_threads": table[0][1], "kick_rows": table[0][2], "kick_drift_width": table[0][3],
-            "kick_drift_blocks": table[0][4], "us_per_step": table[0][0],
+    best = {"drift_threads": pick[1], "kick_rows": pick[2], "kick_drift_width": pick[3],
+            "kick_drift_blocks": pick[4], "us_per_step": pick[0],
             "table": [{"drift_threads": nt, "kick_rows": kr, "kick_drift_width": kw, "kick_drift_blocks": kb,
                        "us_per_step": t} for t, nt, kr, kw, kb in table]}
     _store(key, best)
