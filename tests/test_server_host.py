@@ -68,3 +68,14 @@ def test_create_arguments(V):
     assert lib.vlasov_server_create(C.c_void_p(1 << 20), 1 << 30, None, 1, 65, 16, 1, C.byref(srv)) == V.E_INVAL
     assert lib.vlasov_server_create(C.c_void_p(1 << 20), 1 << 30, None, 2, 8, 16, 1, C.byref(srv)) == V.E_INVAL
     assert lib.vlasov_server_create(C.c_void_p(1 << 20), 1 << 30, None, 1, 8, 0, 1, C.byref(srv)) == V.E_INVAL
+
+
+@pytest.mark.parametrize("kw", [dict(spline=I.SPLINE_GS), dict(splitting=I.SPLIT_TRIPLE_JUMP),
+                                dict(splitting=I.SPLIT_SUZUKI), dict(filter_every=2, filter_strength=0.5)])
+def test_the_server_runs_the_strang_local_spline_only(V, kw):
+    lib = V.load()
+    p = I.Params(I.MODEL_HMF, 128, 64, -math.pi, math.pi, -2.0, 2.0, 0.1, storage=1, **kw)
+    srv = _server(V, lib.vlasov_server_table_bytes(16) + 4 * V.request_footprint(p))
+    assert _submit(V, srv, p) == V.E_INVAL
+    assert "only" in lib.vlasov_last_error().decode()
+    assert lib.vlasov_server_destroy(srv) == 0
