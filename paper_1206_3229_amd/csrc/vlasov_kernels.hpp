@@ -206,10 +206,11 @@ __device__ __forceinline__ void store_run(T *row, int i, int nx, const T (&o)[V]
 // Steps 1 and 4 (eqs. step1, step4): drift along x, row j shifted by the
 // constant p_j tau/dx cells.  NPASS = 2 applies two half drifts in turn (the
 // second half drift of one (sub)step and the first of the next, tables 1 and
-// 2: equal for the Strang splitting), keeping the intermediate row in LDS.  One workgroup of NT threads: TW consecutive
-// columns of a block of 16 consecutive rows, runs of V adjacent columns per
-// thread; TW = V NT - TRIM (a trim keeps the TW + 9 intermediate values of the
-// two-pass form within one run per thread).  Rows stream through two LDS window
+// 2: equal for the Strang splitting), keeping the intermediate row in LDS.
+// One workgroup of NT threads: TW consecutive columns of a block of 16
+// consecutive rows, runs of V adjacent columns per thread; TW = V NT - TRIM
+// (a trim keeps the TW + 9 intermediate values of the two-pass form within
+// one run per thread).  Rows stream through two LDS window
 // buffers; the window of each row (TW columns plus the stencil and shift halo,
 // periodic wrap or zeros) is requested PF rows ahead of its use and held in
 // registers meanwhile.  With PARTIALS, also writes the serial column sum of the
