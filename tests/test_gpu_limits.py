@@ -1,7 +1,7 @@
-"""Edge sizes on the device: the longest rows and columns the library takes,
+"""Edge cases on the device: the longest rows and columns the library takes,
 a grid whose buffers pass 2 GiB (byte offsets beyond 32 bits), the largest
-global-spline lines, and the 4096^2 sheet in every launch shape the
-autotuner can pick for the benchmark."""
+global-spline lines, the 4096^2 sheet in every launch shape the autotuner can
+pick for the benchmark, a negative time step and an empty distribution."""
 import math
 
 import numpy as np
@@ -102,3 +102,28 @@ def test_sheet_4096_in_every_launch_shape(V, oracle, storage):
     for shape in V.tuning_candidates():
         _log(f"sheet 4096 storage={storage} shape={shape}")
         assert np.array_equal(_run(V, p, f0, 2, shape), want), shape
+
+
+@pytest.mark.parametrize("model", [I.MODEL_HMF, I.MODEL_SHEET])
+def test_negative_time_step(V, oracle, model):
+    # dt < 0 runs the characteristics backwards: feet on the other side, same rules
+    if model == I.MODEL_HMF:
+        p = I.Params(I.MODEL_HMF, 300, 64, -math.pi, math.pi, -2.5, 2.5, -0.05)
+        th0, p0 = I.waterbag_halfwidths(0.5, 0.69)
+        f0 = I.waterbag(p, th0, p0, 1e-4, 3)
+    else:
+        p = I.Params(I.MODEL_SHEET, 260, 48, -10.0, 10.0, -4.0, 4.0, -0.03, bc_x=I.BC_ZERO)
+        f0 = I.waterbag(p, 1.0, 0.5, 1e-4, 3)
+    want = oracle.run(p, f0, 6)
+    for shape in [(128, 16, 0, 1), (128, 16, 256, 1)]:
+        assert np.array_equal(_run(V, p, f0, 6, shape), want), shape
+
+
+def test_empty_distribution_stays_empty(V):
+    p = I.Params(I.MODEL_SHEET, 64, 64, -10.0, 10.0, -4.0, 4.0, 0.05, bc_x=I.BC_ZERO)
+    s = V.Solver(p, np.zeros((64, 64)))
+    s.step(5)
+    f, m = s.read_f(), s.moments()
+    s.close()
+    assert not f.any()
+    assert all(v == 0.0 for v in m.values()), m
