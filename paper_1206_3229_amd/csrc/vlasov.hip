@@ -437,8 +437,8 @@ int launch_kick_drift_t(vlasov_ctx *c, int ta, double h)
     double *part = c->at<double>(c->L.part);
     const int nx = (int)P.nx, np = (int)P.np;
 #define KD_LAUNCH(BX, BP)                                                                                            \
-    launch(c, VLASOV_K_KICK_DRIFT2, vk::k_kick_drift<T, 2, BX, BP, true, NT, TW, KD_PF, RB>, grid, dim3(NT), fin, fout, \
-           F, h, c->dp, dm1, dw1, dm2, dw2, kbase, krel, part, nx, np, ntx, nty)
+    launch(c, VLASOV_K_KICK_DRIFT2, vk::k_kick_drift<T, 2, BX, BP, true, NT, TW, kd_pf<T>(), RB>, grid, dim3(NT), fin,  \
+           fout, F, h, c->dp, dm1, dw1, dm2, dw2, kbase, krel, part, nx, np, ntx, nty)
     if (P.bc_x == VLASOV_BC_PERIODIC) {
         if (P.bc_p == VLASOV_BC_PERIODIC) KD_LAUNCH(vk::BC_PERIODIC, vk::BC_PERIODIC); else KD_LAUNCH(vk::BC_PERIODIC, vk::BC_ZERO);
     } else {

@@ -33,8 +33,11 @@ inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 constexpr int DRIFT_NT = 128, DRIFT_V = 2, DRIFT_PF = 4;
 // kick rows per thread (measured best on 4096^2: 16 for FP64, 32 for FP32)
 template <typename T> constexpr int kick_rows() { return sizeof(T) == 8 ? 16 : 32; }
-// fused kick and drift: default tile width, rows requested ahead by the kick
-constexpr int KD_TW = 256, KD_RB = 1, KD_PF = 4;
+// fused kick and drift: default tile width and blocks; rows requested ahead
+// by the kick (FP64: 2, which keeps the kernel within 96 VGPRs, five waves
+// per SIMD)
+constexpr int KD_TW = 256, KD_RB = 1;
+template <typename T> constexpr int kd_pf() { return sizeof(T) == 8 ? 2 : 4; }
 // rows per thread of the filter along p
 constexpr int FILTER_R = 16;
 // substeps of a step at most (the splittings of vlasov_splitting)

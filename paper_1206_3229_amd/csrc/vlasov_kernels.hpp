@@ -157,6 +157,9 @@ __device__ __forceinline__ bool xcd_tile(int ntx, int nty, int &tx, int &ty)
 template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
+template <typename T> struct Vec4;
+template <> struct Vec4<double> { using type = double4; };
+template <> struct Vec4<float> { using type = float4; };
 
 // Interpolates the V adjacent outputs q = V u .. V u + V - 1 of a row from an
 // LDS window `src` (the sample at the start of output q's cell is src[q + 4]):
@@ -593,7 +596,7 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
                                                 const int32_t *__restrict__ dm2, const double4 *__restrict__ dw2,
                                                 const int32_t *__restrict__ kbase, const int32_t *__restrict__ krel,
                                                 double *__restrict__ part, int nx, int np, int tx, int ty, T *win0,
-                                                T *win1, T *mid)
+                                                T *win1, T *mid, typename Vec4<T>::type *kwt)
 {
     using KG = KickDriftGeom<NPASS, NT, TW, VR>;
     using G = typename KG::G;
@@ -623,6 +626,10 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
     int rbase[KC];  // row of sample 0 of the current block (wrapped or unclamped)
     uint32_t inside[KC];
     bool colin[KC];
+    // FP64: the spline weights of the kicked columns live in LDS (slot t +
+    // k NT, read back by the same thread each row), which keeps the kernel
+    // within 96 VGPRs; FP32 keeps them in registers
+    constexpr bool KWL = sizeof(T) == 8;
     T ka[KC], kb[KC], kg[KC], kd[KC];
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
@@ -638,10 +645,19 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
         }
         const Foot ft = foot_of_shift((F[gc] * dt) / dp);
         const int m = reduce_offset(ft.m, np, BCP);
-        ka[k] = (T)ft.a;
-        kb[k] = (T)ft.b;
-        kg[k] = (T)ft.g;
-        kd[k] = (T)ft.d;
+        if constexpr (KWL) {
+            typename Vec4<T>::type kw;
+            kw.x = (T)ft.a;
+            kw.y = (T)ft.b;
+            kw.z = (T)ft.g;
+            kw.w = (T)ft.d;
+            kwt[t + k * NT] = kw;
+        } else {
+            ka[k] = (T)ft.a;
+            kb[k] = (T)ft.b;
+            kg[k] = (T)ft.g;
+            kd[k] = (T)ft.d;
+        }
         colp[k] = fin + gc;
         int b = j0 + m - 4;
         if (BCP == BC_PERIODIC) b = wrap(b, np);
@@ -705,7 +721,13 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
 #pragma unroll
                 for (int k = 0; k < KC; ++k) {
                     const T Dk1 = second_diff(w[k] + r + 5);
-                    T y = spline(ka[k], kb[k], kg[k], kd[k], w[k][r + 4], w[k][r + 5], Dk[k], Dk1);
+                    T y;
+                    if constexpr (KWL) {
+                        const typename Vec4<T>::type kw = kwt[t + k * NT];
+                        y = spline(kw.x, kw.y, kw.z, kw.w, w[k][r + 4], w[k][r + 5], Dk[k], Dk1);
+                    } else {
+                        y = spline(ka[k], kb[k], kg[k], kd[k], w[k][r + 4], w[k][r + 5], Dk[k], Dk1);
+                    }
                     Dk[k] = Dk1;
                     if (BCX != BC_PERIODIC) y = colin[k] ? y : T(0);
                     const int pos = t + k * NT - rel;
@@ -787,11 +809,12 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
     }
 }
 
-// FP32: six waves per SIMD (at most 80 VGPRs) measured faster than the
-// compiler's own five, despite a few spilled registers.
+// Waves per SIMD: FP64 five (within 96 VGPRs with the kick weights in LDS
+// and two rows of prefetch); FP32 six (at most 80 VGPRs), measured faster
+// than the compiler's own five despite a few spilled registers.
 template <typename T, int NPASS, int BCX, int BCP, bool PARTIALS, int NT, int TW, int PF, int RB, int VR = 2,
           int UB = 1>
-static __global__ __launch_bounds__(NT, sizeof(T) == 8 ? 4 : 6) void k_kick_drift(const T *__restrict__ fin, T *__restrict__ fout,
+static __global__ __launch_bounds__(NT, sizeof(T) == 8 ? 5 : 6) void k_kick_drift(const T *__restrict__ fin, T *__restrict__ fout,
                                                    const double *__restrict__ F, double dt, double dp,
                                                    const int32_t *__restrict__ dm1,
                                                    const double4 *__restrict__ dw1,
@@ -804,15 +827,16 @@ static __global__ __launch_bounds__(NT, sizeof(T) == 8 ? 4 : 6) void k_kick_drif
     using G = typename KickDriftGeom<NPASS, NT, TW, VR>::G;
     __shared__ __attribute__((aligned(16))) T win[2][G::LDA];
     __shared__ __attribute__((aligned(16))) T mid[2 * G::LDM];  // two intermediate rows
+    __shared__ typename Vec4<T>::type kwt[sizeof(T) == 8 ? KickDriftGeom<NPASS, NT, TW, VR>::KC * NT : 1];
     int tx, ty;
     if (!xcd_tile(ntx, nty, tx, ty)) return;
     const bool full = (ty + 1) * (ROWS_PER_BLOCK * RB) <= np && (tx + 1) * TW <= nx && (nx & 1) == 0;
     if (full)
         kick_drift_tile<T, NPASS, BCX, BCP, PARTIALS, NT, TW, PF, RB, VR, UB, true>(
-            fin, fout, F, dt, dp, dm1, dw1, dm2, dw2, kbase, krel, part, nx, np, tx, ty, win[0], win[1], mid);
+            fin, fout, F, dt, dp, dm1, dw1, dm2, dw2, kbase, krel, part, nx, np, tx, ty, win[0], win[1], mid, kwt);
     else
         kick_drift_tile<T, NPASS, BCX, BCP, PARTIALS, NT, TW, PF, RB, VR, UB, false>(
-            fin, fout, F, dt, dp, dm1, dw1, dm2, dw2, kbase, krel, part, nx, np, tx, ty, win[0], win[1], mid);
+            fin, fout, F, dt, dp, dm1, dw1, dm2, dw2, kbase, krel, part, nx, np, tx, ty, win[0], win[1], mid, kwt);
 }
 
 // ---------------------------------------------------------------------------
