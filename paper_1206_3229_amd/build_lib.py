@@ -1,19 +1,25 @@
 """Compile the HIP library for gfx950 (in-tree, no JIT cache).
 
+Every translation unit under csrc/ is compiled on its own (in parallel), then
+linked into libvlasov.so.
+
     python -m paper_1206_3229_amd.build_lib
 """
 from __future__ import annotations
 
+import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = [os.path.join(PKG, "csrc", "vlasov.hip"), os.path.join(PKG, "csrc", "vlasov_batch.hip")]
-DEPS = SRC + [os.path.join(PKG, "csrc", n) for n in ("vlasov_kernels.hpp", "vlasov_internal.hpp")] + \
-    [os.path.join(ROOT, "include", "vlasov.h")]
+CSRC = os.path.join(PKG, "csrc")
+SRC = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+DEPS = SRC + sorted(glob.glob(os.path.join(CSRC, "*.hpp"))) + [os.path.join(ROOT, "include", "vlasov.h")]
 LIB = os.path.join(PKG, "libvlasov.so")
+OBJDIR = os.path.join(PKG, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -21,7 +27,6 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # IEEE arithmetic exactly as written: no contraction into FMA, no fast math.
     "-ffp-contract=off",
     "-fno-fast-math",
@@ -34,9 +39,25 @@ FLAGS = [
 ]
 
 
+def _jobs() -> int:
+    return max(1, min(len(SRC), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1)), 16))
+
+
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJDIR, os.path.basename(src)[:-4] + ".o")
+    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return obj
+
+
 def build(verbose: bool = False) -> str:
+    os.makedirs(OBJDIR, exist_ok=True)
+    with ThreadPoolExecutor(_jobs()) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SRC))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *SRC, "-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -52,5 +73,5 @@ def stale() -> bool:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose="-v" in sys.argv))
     sys.exit(0)

@@ -111,92 +111,6 @@ std::string validate(const vlasov_params *p)
 
 namespace {
 
-hipEvent_t take_event(vlasov_ctx *c)
-{
-    if (!c->pool.empty()) {
-        hipEvent_t e = c->pool.back();
-        c->pool.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-}
-
-// Launches a kernel on the context's stream.  When profiling is on, the
-// launch carries its own start/stop events (recorded by the dispatch itself,
-// so no extra packets sit between consecutive kernels).
-template <typename... KArgs, typename... Args>
-void launch(vlasov_ctx *c, int kid, void (*kernel)(KArgs...), dim3 grid, dim3 block, Args... args)
-{
-    if (c->prof) {
-        hipEvent_t a = take_event(c), b = take_event(c);
-        if (a && b) {
-            hipExtLaunchKernelGGL(kernel, grid, block, 0, c->stream, a, b, 0, static_cast<KArgs>(args)...);
-            c->recs.push_back({kid, a, b});
-            return;
-        }
-    }
-    kernel<<<grid, block, 0, c->stream>>>(static_cast<KArgs>(args)...);
-}
-
-int check_launch(const char *what)
-{
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(VLASOV_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
-    return VLASOV_OK;
-}
-
-template <typename T, int NT>
-int launch_drift_nt(vlasov_ctx *c, int ta, int tb, bool partials)
-{
-    const int npass = tb >= 0 ? 2 : 1;
-    const vlasov_params &P = c->P;
-    const int tw = vk::DriftShape<NT, DRIFT_V, 0>::TW;  // columns per workgroup
-    const int ntx = (int)((P.nx + tw - 1) / tw), nty = (int)c->nblk;
-    const dim3 grid((unsigned)vk::xcd_grid(ntx, nty));
-    const T *fin = (const T *)c->fcur();
-    T *fout = (T *)c->fnext();
-    const int32_t *dm1 = c->dm(ta), *dm2 = c->dm(tb >= 0 ? tb : ta);
-    const double4 *dw1 = c->dw(ta), *dw2 = c->dw(tb >= 0 ? tb : ta);
-    double *part = c->at<double>(c->L.part);
-    const int nx = (int)P.nx, np = (int)P.np;
-    const int kid = npass == 2 ? VLASOV_K_DRIFT2 : VLASOV_K_DRIFT;
-#define DRIFT_LAUNCH(NP, BC, PT)                                                                                      \
-    launch(c, kid, vk::k_drift<T, NP, BC, PT, NT, DRIFT_V, 0, DRIFT_PF>, grid, dim3(NT), fin, fout, dm1, dw1, dm2,   \
-           dw2, part, nx, np, ntx, nty)
-    if (P.bc_x == VLASOV_BC_PERIODIC) {
-        if (npass == 2) {
-            if (partials) DRIFT_LAUNCH(2, vk::BC_PERIODIC, true); else DRIFT_LAUNCH(2, vk::BC_PERIODIC, false);
-        } else {
-            if (partials) DRIFT_LAUNCH(1, vk::BC_PERIODIC, true); else DRIFT_LAUNCH(1, vk::BC_PERIODIC, false);
-        }
-    } else {
-        if (npass == 2) {
-            if (partials) DRIFT_LAUNCH(2, vk::BC_ZERO, true); else DRIFT_LAUNCH(2, vk::BC_ZERO, false);
-        } else {
-            if (partials) DRIFT_LAUNCH(1, vk::BC_ZERO, true); else DRIFT_LAUNCH(1, vk::BC_ZERO, false);
-        }
-    }
-#undef DRIFT_LAUNCH
-    int rc = check_launch("drift");
-    if (rc == VLASOV_OK) c->cur ^= 1;
-    return rc;
-}
-
-template <typename T>
-int launch_drift(vlasov_ctx *c, int ta, int tb, bool partials)
-{
-    switch (c->tune.drift_threads) {
-    case 64:
-        return launch_drift_nt<T, 64>(c, ta, tb, partials);
-    case 256:
-        return launch_drift_nt<T, 256>(c, ta, tb, partials);
-    default:
-        return launch_drift_nt<T, 128>(c, ta, tb, partials);
-    }
-}
-
 int gs_drift(vlasov_ctx *c, int table, bool partials);
 int gs_kick(vlasov_ctx *c, double h);
 
@@ -253,40 +167,6 @@ int density_force(vlasov_ctx *c)
     return rc;
 }
 
-template <typename T, int KR>
-int launch_kick_r(vlasov_ctx *c, double h)
-{
-    const vlasov_params &P = c->P;
-    const int ntx = (int)((P.nx + 255) / 256), nty = (int)((P.np + KR - 1) / KR);
-    const dim3 grid((unsigned)vk::xcd_grid(ntx, nty));
-    const T *fin = (const T *)c->fcur();
-    T *fout = (T *)c->fnext();
-    const double *F = force_ptr(c);
-    if (P.bc_p == VLASOV_BC_PERIODIC)
-        launch(c, VLASOV_K_KICK, vk::k_kick<T, vk::BC_PERIODIC, KR>, grid, dim3(256), fin, fout, F, h, c->dp,
-               (int)P.nx, (int)P.np, ntx, nty);
-    else
-        launch(c, VLASOV_K_KICK, vk::k_kick<T, vk::BC_ZERO, KR>, grid, dim3(256), fin, fout, F, h, c->dp,
-               (int)P.nx, (int)P.np, ntx, nty);
-    int rc = check_launch("kick");
-    if (rc == VLASOV_OK) c->cur ^= 1;
-    return rc;
-}
-
-template <typename T>
-int launch_kick(vlasov_ctx *c, double h)
-{
-    switch (c->tune.kick_rows) {
-    case 8:
-        return launch_kick_r<T, 8>(c, h);
-    case 16:
-        return launch_kick_r<T, 16>(c, h);
-    default:
-        return launch_kick_r<T, 32>(c, h);
-    }
-}
-
-// Kick of step size h (w_k dt) with the last force.
 int kick(vlasov_ctx *c, double h)
 {
     if (c->P.spline == VLASOV_SPLINE_GS) return gs_kick(c, h);
@@ -294,54 +174,12 @@ int kick(vlasov_ctx *c, double h)
 }
 
 // The filter along p with strength sigma = filter_strength.
-template <typename T>
-int launch_filter(vlasov_ctx *c)
-{
-    const vlasov_params &P = c->P;
-    const int ntx = (int)((P.nx + 255) / 256), nty = (int)((P.np + FILTER_R - 1) / FILTER_R);
-    const dim3 grid((unsigned)vk::xcd_grid(ntx, nty));
-    const T *fin = (const T *)c->fcur();
-    T *fout = (T *)c->fnext();
-    const double cf = P.filter_strength / 256.0;
-    if (P.bc_p == VLASOV_BC_PERIODIC)
-        launch(c, VLASOV_K_FILTER, vk::k_filter_p<T, vk::BC_PERIODIC, FILTER_R>, grid, dim3(256), fin, fout, cf,
-               (int)P.nx, (int)P.np, ntx, nty);
-    else
-        launch(c, VLASOV_K_FILTER, vk::k_filter_p<T, vk::BC_ZERO, FILTER_R>, grid, dim3(256), fin, fout, cf,
-               (int)P.nx, (int)P.np, ntx, nty);
-    int rc = check_launch("filter");
-    if (rc == VLASOV_OK) c->cur ^= 1;
-    return rc;
-}
-
 int filter(vlasov_ctx *c)
 {
     return c->P.storage == VLASOV_F32 ? launch_filter<float>(c) : launch_filter<double>(c);
 }
 
 // Kick of step size h and the filter in one pass (local spline).
-template <typename T>
-int launch_kick_filter(vlasov_ctx *c, double h)
-{
-    const vlasov_params &P = c->P;
-    const int ntx = (int)((P.nx + 255) / 256), nty = (int)((P.np + FILTER_R - 1) / FILTER_R);
-    const dim3 grid((unsigned)vk::xcd_grid(ntx, nty));
-    const T *fin = (const T *)c->fcur();
-    T *fout = (T *)c->fnext();
-    const double cf = P.filter_strength / 256.0;
-    if (P.bc_p == VLASOV_BC_PERIODIC)
-        launch(c, VLASOV_K_FILTER, vk::k_kick_filter<T, vk::BC_PERIODIC, FILTER_R>, grid, dim3(256), fin, fout,
-               force_ptr(c), h, c->dp, cf, (int)P.nx, (int)P.np, ntx, nty);
-    else
-        launch(c, VLASOV_K_FILTER, vk::k_kick_filter<T, vk::BC_ZERO, FILTER_R>, grid, dim3(256), fin, fout,
-               force_ptr(c), h, c->dp, cf, (int)P.nx, (int)P.np, ntx, nty);
-    int rc = check_launch("kick and filter");
-    if (rc == VLASOV_OK) c->cur ^= 1;
-    return rc;
-}
-
-// The kick followed by the filter: one pass with the local spline, the
-// transposed kick and then the filter with the global spline.
 int kick_filter(vlasov_ctx *c, double h)
 {
     if (c->P.spline == VLASOV_SPLINE_GS) {
@@ -355,56 +193,6 @@ int kick_filter(vlasov_ctx *c, double h)
 // Global spline (eq. tridiagsys): one workgroup per line; the kick runs on the
 // rows of the transpose.
 // ---------------------------------------------------------------------------
-template <typename T>
-int gs_drift_t(vlasov_ctx *c, int table, bool partials)
-{
-    const vlasov_params &P = c->P;
-    const T *fin = (const T *)c->fcur();
-    T *fout = (T *)c->fnext();
-    const int32_t *dm = c->dm(table);
-    const double4 *dw = c->dw(table);
-    const double *g = c->at<double>(c->L.gs_g);
-    const double *nof = nullptr;
-    if (P.bc_x == VLASOV_BC_PERIODIC)
-        launch(c, VLASOV_K_DRIFT, vk::k_gs_line<T, vk::BC_PERIODIC, false>, dim3((unsigned)P.np), dim3(vk::GS_NT), fin,
-               fout, (int)P.nx, dm, dw, nof, 0.0, 0.0, g);
-    else
-        launch(c, VLASOV_K_DRIFT, vk::k_gs_line<T, vk::BC_ZERO, false>, dim3((unsigned)P.np), dim3(vk::GS_NT), fin,
-               fout, (int)P.nx, dm, dw, nof, 0.0, 0.0, g);
-    int rc = check_launch("global-spline drift");
-    if (rc) return rc;
-    c->cur ^= 1;
-    if (partials) {
-        launch(c, VLASOV_K_DRIFT, vk::k_partials<T>, dim3((unsigned)((P.nx + 255) / 256), (unsigned)c->nblk),
-               dim3(256), (const T *)c->fcur(), c->at<double>(c->L.part), (int)P.nx, (int)P.np);
-        rc = check_launch("partial sums");
-    }
-    return rc;
-}
-
-template <typename T>
-int gs_kick_t(vlasov_ctx *c, double h)
-{
-    const vlasov_params &P = c->P;
-    const int nx = (int)P.nx, np = (int)P.np;
-    T *A = (T *)c->fcur(), *B = (T *)c->fnext();
-    const unsigned t1 = (unsigned)(((nx + 63) / 64) * ((np + 63) / 64));
-    launch(c, VLASOV_K_KICK, vk::k_transpose<T>, dim3(t1), dim3(256), (const T *)A, B, np, nx);  // B = A^T
-    const int32_t *nodm = nullptr;
-    const double4 *nodw = nullptr;
-    const double *g = c->at<double>(c->L.gs_g);
-    if (P.bc_p == VLASOV_BC_PERIODIC)
-        launch(c, VLASOV_K_KICK, vk::k_gs_line<T, vk::BC_PERIODIC, true>, dim3((unsigned)nx), dim3(vk::GS_NT),
-               (const T *)B, A, np, nodm, nodw, force_ptr(c), h, c->dp, g);
-    else
-        launch(c, VLASOV_K_KICK, vk::k_gs_line<T, vk::BC_ZERO, true>, dim3((unsigned)nx), dim3(vk::GS_NT),
-               (const T *)B, A, np, nodm, nodw, force_ptr(c), h, c->dp, g);
-    launch(c, VLASOV_K_KICK, vk::k_transpose<T>, dim3(t1), dim3(256), (const T *)A, B, nx, np);  // B = A^T
-    int rc = check_launch("global-spline kick");
-    if (rc == VLASOV_OK) c->cur ^= 1;
-    return rc;
-}
-
 int gs_drift(vlasov_ctx *c, int table, bool partials)
 {
     return c->P.storage == VLASOV_F32 ? gs_drift_t<float>(c, table, partials) : gs_drift_t<double>(c, table, partials);
@@ -417,56 +205,6 @@ int gs_kick(vlasov_ctx *c, double h)
 
 // Fused kick and two half drifts (+ density partial sums) on tiles of TW
 // columns by RB density blocks.
-template <typename T, int TW, int RB>
-int launch_kick_drift_t(vlasov_ctx *c, int ta, double h)
-{
-    // whole wavefronts, about 5/8 TW threads: one first-pass run and up to two
-    // kicked columns per thread
-    constexpr int NT = (TW / 8 * 5 + 63) / 64 * 64;
-    const vlasov_params &P = c->P;
-    const int ntx = (int)((P.nx + TW - 1) / TW), nty = (int)((c->nblk + RB - 1) / RB);
-    const dim3 grid((unsigned)vk::xcd_grid(ntx, nty));
-    const T *fin = (const T *)c->fcur();
-    T *fout = (T *)c->fnext();
-    const double *F = force_ptr(c);
-    const int tb = (ta + 1) % c->nsub;
-    const int32_t *dm1 = c->dm(ta), *dm2 = c->dm(tb);
-    const double4 *dw1 = c->dw(ta), *dw2 = c->dw(tb);
-    const int32_t *kbase = c->at<int32_t>(c->L.kd_base) + (size_t)ta * (size_t)c->nblk;
-    const int32_t *krel = c->at<int32_t>(c->L.kd_rel) + (size_t)ta * (size_t)P.np;
-    double *part = c->at<double>(c->L.part);
-    const int nx = (int)P.nx, np = (int)P.np;
-#define KD_LAUNCH(BX, BP)                                                                                            \
-    launch(c, VLASOV_K_KICK_DRIFT2, vk::k_kick_drift<T, 2, BX, BP, true, NT, TW, kd_pf<T>(), RB>, grid, dim3(NT), fin,  \
-           fout, F, h, c->dp, dm1, dw1, dm2, dw2, kbase, krel, part, nx, np, ntx, nty)
-    if (P.bc_x == VLASOV_BC_PERIODIC) {
-        if (P.bc_p == VLASOV_BC_PERIODIC) KD_LAUNCH(vk::BC_PERIODIC, vk::BC_PERIODIC); else KD_LAUNCH(vk::BC_PERIODIC, vk::BC_ZERO);
-    } else {
-        if (P.bc_p == VLASOV_BC_PERIODIC) KD_LAUNCH(vk::BC_ZERO, vk::BC_PERIODIC); else KD_LAUNCH(vk::BC_ZERO, vk::BC_ZERO);
-    }
-#undef KD_LAUNCH
-    int rc = check_launch("kick+drift");
-    if (rc == VLASOV_OK) c->cur ^= 1;
-    return rc;
-}
-
-template <typename T, int TW>
-int launch_kick_drift_w(vlasov_ctx *c, int ta, double h)
-{
-    switch (c->kd_rb) {
-    case 4:
-        return launch_kick_drift_t<T, TW, 4>(c, ta, h);
-    case 2:
-        return launch_kick_drift_t<T, TW, 2>(c, ta, h);
-    default:
-        return launch_kick_drift_t<T, TW, 1>(c, ta, h);
-    }
-}
-
-// Kick k (step size h), the filter if `filt`, then the half drift of table k
-// and (tb >= 0, then with partial sums) that of table tb = k + 1 mod nsub:
-// the fused kernel where the tables allow it and the launch shape asks for
-// it, else the separate kernels.
 int kick_then_drift(vlasov_ctx *c, int k, int tb, double h, bool filt)
 {
     const int w = c->tune.kick_drift_width;

@@ -116,4 +116,59 @@ inline const double *force_ptr(const vlasov_ctx *c)
 {
     return c->at<double>(c->P.model == VLASOV_MODEL_EXTERNAL ? c->L.Fext : c->L.F);
 }
+
+inline hipEvent_t take_event(vlasov_ctx *c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launches a kernel on the context's stream.  When profiling is on, the
+// launch carries its own start/stop events (recorded by the dispatch itself,
+// so no extra packets sit between consecutive kernels).
+template <typename... KArgs, typename... Args>
+void launch(vlasov_ctx *c, int kid, void (*kernel)(KArgs...), dim3 grid, dim3 block, Args... args)
+{
+    if (c->prof) {
+        hipEvent_t a = take_event(c), b = take_event(c);
+        if (a && b) {
+            hipExtLaunchKernelGGL(kernel, grid, block, 0, c->stream, a, b, 0, static_cast<KArgs>(args)...);
+            c->recs.push_back({kid, a, b});
+            return;
+        }
+    }
+    kernel<<<grid, block, 0, c->stream>>>(static_cast<KArgs>(args)...);
+}
+
+inline int check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VLASOV_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return VLASOV_OK;
+}
+
+// Launchers (one translation unit per kernel family).  Each enqueues its
+// kernel on the context's stream and, on success, makes the output buffer
+// the current f.
+// Half drift of table ta, then (tb >= 0) that of table tb, in one pass; with
+// partials the density partial sums of the result.
+template <typename T> int launch_drift(vlasov_ctx *c, int ta, int tb, bool partials);
+// Kick of step size h with the last force.
+template <typename T> int launch_kick(vlasov_ctx *c, double h);
+// The filter along p; the kick of step size h followed by the filter.
+template <typename T> int launch_filter(vlasov_ctx *c);
+template <typename T> int launch_kick_filter(vlasov_ctx *c, double h);
+// Global spline: half drift of table `table` (and its partial sums); kick.
+template <typename T> int gs_drift_t(vlasov_ctx *c, int table, bool partials);
+template <typename T> int gs_kick_t(vlasov_ctx *c, double h);
+// Kick of substep ta (step size h) fused with the half drifts of tables ta
+// and ta + 1 mod nsub, on tiles of TW columns.
+template <typename T, int TW> int launch_kick_drift_w(vlasov_ctx *c, int ta, double h);
 }  // namespace vlasov_detail
+
