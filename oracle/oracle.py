@@ -16,7 +16,7 @@ SRC = os.path.join(HERE, "vlasov_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 # R8: sin and cos are called on their own (no merging into sincos)
-CFLAGS = ["-O2", "-fPIC", "-shared", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+CFLAGS = ["-O2", "-fPIC", "-shared", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
           "-fno-builtin-sin", "-fno-builtin-cos", "-fno-builtin-sincos",
           "-Wall", "-Wextra", "-Wno-unused-parameter"]
 
@@ -69,6 +69,10 @@ def _load():
         lib.oracle_filter_p.argtypes = [PP, _D, _D]
         lib.oracle_split_weights.argtypes = [C.c_int, _D]
         lib.oracle_split_weights.restype = C.c_int
+        lib.oracle_set_threads.argtypes = [C.c_int]
+        lib.oracle_set_threads.restype = None
+        lib.oracle_get_threads.argtypes = []
+        lib.oracle_get_threads.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -88,6 +92,15 @@ def _ptr(a: np.ndarray):
 
 def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (the results do not depend on it)."""
+    _load().oracle_set_threads(int(n))
+
+
+def threads() -> int:
+    return int(_load().oracle_get_threads())
 
 
 def split_weights(scheme: int) -> list[float]:

@@ -16,6 +16,13 @@
  * rounded exactly where written, and fused multiply-adds appear only as
  * explicit fma()/fmaf() calls.
  *
+ * Threads (OpenMP, compiled with -fopenmp): the work is split over whole
+ * lines only (rows of a drift, columns of a kick, a density, a filter or a
+ * moment, outputs of the ring convolution).  Every line is computed by one
+ * thread exactly as the serial loop would, and sums that run over lines are
+ * accumulated afterwards in line order, so results do not depend on the
+ * number of threads.
+ *
  * Where the paper is silent the following readings are used (each one is
  * restated where it is applied):
  *   R1  the second difference of eq. (findif) carries no 1/du^2; the spline
@@ -57,6 +64,7 @@
  *       every p-moment of degree below 8 of each column.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -323,6 +331,7 @@ static double node_p(const oracle_params *P, int64_t j) { return P->pmin + (doub
 void oracle_advect_x(const oracle_params *P, const double *f, double *out, double tau)
 {
     double dx = grid_dx(P);
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < P->np; j++) {
         double shift = (node_p(P, j) * tau) / dx;
         interpolate(P, f + j * P->nx, out + j * P->nx, P->nx, 1, shift, P->bc_x);
@@ -334,9 +343,20 @@ void oracle_advect_x(const oracle_params *P, const double *f, double *out, doubl
 void oracle_advect_p(const oracle_params *P, const double *f, double *out, const double *F, double dt)
 {
     double dp = grid_dp(P);
-    for (int64_t i = 0; i < P->nx; i++) {
-        double shift = (F[i] * dt) / dp;
-        interpolate(P, f + i, out + i, P->np, P->nx, shift, P->bc_p);
+    const int64_t nx = P->nx, np = P->np;
+#pragma omp parallel
+    {
+        /* each column is copied to a contiguous line, moved, and copied back */
+        double *line = malloc((size_t)np * sizeof(double)), *moved = malloc((size_t)np * sizeof(double));
+#pragma omp for schedule(static, 64)
+        for (int64_t i = 0; i < nx; i++) {
+            double shift = (F[i] * dt) / dp;
+            for (int64_t j = 0; j < np; j++) line[j] = f[j * nx + i];
+            interpolate(P, line, moved, np, 1, shift, P->bc_p);
+            for (int64_t j = 0; j < np; j++) out[j * nx + i] = moved[j];
+        }
+        free(line);
+        free(moved);
     }
 }
 
@@ -396,6 +416,7 @@ static double column_sum(const oracle_params *P, const double *f, int64_t i, con
 void oracle_density(const oracle_params *P, const double *f, double *rho)
 {
     double dp = grid_dp(P);
+#pragma omp parallel for schedule(static, 64)
     for (int64_t i = 0; i < P->nx; i++) rho[i] = dp * column_sum(P, f, i, NULL, TERM_F);
 }
 
@@ -470,6 +491,7 @@ void oracle_force(const oracle_params *P, const double *rho, const double *F_ext
         }
     } else if (P->model == MODEL_RING) {
         /* F_i = -dx sum_k V'(x_i - x_k) rho_k, direct periodic convolution */
+#pragma omp parallel for schedule(static, 16)
         for (int64_t i = 0; i < n; i++) {
             sum64 s;
             sum64_init(&s);
@@ -525,6 +547,7 @@ void oracle_force(const oracle_params *P, const double *rho, const double *F_ext
 void oracle_filter_p(const oracle_params *P, const double *f, double *out)
 {
     const double c = P->filter_strength / 256.0;
+#pragma omp parallel for schedule(static, 64)
     for (int64_t i = 0; i < P->nx; i++) {
         const double *col = f + i;
         for (int64_t j = 0; j < P->np; j++) {
@@ -576,6 +599,7 @@ static void store_round(const oracle_params *P, double *f)
 {
     if (P->storage != STORE_F32) return;
     int64_t N = P->nx * P->np;
+#pragma omp parallel for schedule(static)
     for (int64_t t = 0; t < N; t++) f[t] = (double)(float)f[t];
 }
 
@@ -671,15 +695,26 @@ void oracle_moments(const oracle_params *P, const double *f, double *out)
     sum64_init(&sq);
     sum64_init(&se);
     sum64_init(&sn);
+    /* column quantities (one column per thread), then their sums in column order */
+    double *col = malloc((size_t)(5 * nx) * sizeof(double));
+#pragma omp parallel for schedule(static, 64)
     for (int64_t i = 0; i < nx; i++) {
         rho[i] = dp * column_sum(P, f, i, NULL, TERM_F);
-        sum64_add(&sm, i, rho[i]);
-        sum64_add(&sj, i, dp * column_sum(P, f, i, pw, TERM_F));
-        sum64_add(&sk, i, dp * column_sum(P, f, i, kw, TERM_F));
-        sum64_add(&sq, i, dp * column_sum(P, f, i, NULL, TERM_SQUARE));
-        sum64_add(&se, i, dp * column_sum(P, f, i, NULL, TERM_FLOGF));
-        sum64_add(&sn, i, dp * column_sum(P, f, i, NULL, TERM_NEG));
+        col[i] = dp * column_sum(P, f, i, pw, TERM_F);
+        col[nx + i] = dp * column_sum(P, f, i, kw, TERM_F);
+        col[2 * nx + i] = dp * column_sum(P, f, i, NULL, TERM_SQUARE);
+        col[3 * nx + i] = dp * column_sum(P, f, i, NULL, TERM_FLOGF);
+        col[4 * nx + i] = dp * column_sum(P, f, i, NULL, TERM_NEG);
     }
+    for (int64_t i = 0; i < nx; i++) {
+        sum64_add(&sm, i, rho[i]);
+        sum64_add(&sj, i, col[i]);
+        sum64_add(&sk, i, col[nx + i]);
+        sum64_add(&sq, i, col[2 * nx + i]);
+        sum64_add(&se, i, col[3 * nx + i]);
+        sum64_add(&sn, i, col[4 * nx + i]);
+    }
+    free(col);
     double mass = dx * sum64_total(&sm);
     double mom = dx * sum64_total(&sj);
     double kin = dx * sum64_total(&sk);
@@ -691,8 +726,10 @@ void oracle_moments(const oracle_params *P, const double *f, double *out)
     if (P->model == MODEL_HMF) {
         W = 0.5 * ((mass * mass - mx * mx) - my * my);
     } else if (P->model == MODEL_RING || P->model == MODEL_SHEET) {
-        sum64 sw;
-        sum64_init(&sw);
+        /* phi_i = sum_k V(x_i - x_k) rho_k (one output per thread), then
+         * sum_i phi_i rho_i in order */
+        double *phi = malloc((size_t)nx * sizeof(double));
+#pragma omp parallel for schedule(static, 16)
         for (int64_t i = 0; i < nx; i++) {
             sum64 sphi;
             sum64_init(&sphi);
@@ -702,8 +739,12 @@ void oracle_moments(const oracle_params *P, const double *f, double *out)
                 double v = (P->model == MODEL_RING) ? ring_V_table(P, d) : (double)(i > k ? i - k : k - i);
                 sum64_fma(&sphi, k, v, rho[k]);
             }
-            sum64_fma(&sw, i, sum64_total(&sphi), rho[i]);
+            phi[i] = sum64_total(&sphi);
         }
+        sum64 sw;
+        sum64_init(&sw);
+        for (int64_t i = 0; i < nx; i++) sum64_fma(&sw, i, phi[i], rho[i]);
+        free(phi);
         double coef = (P->model == MODEL_RING) ? (0.5 * dx) * dx : (((M_PI * P->sheet_G) * dx) * dx) * dx;
         W = coef * sum64_total(&sw);
     }
@@ -721,6 +762,10 @@ void oracle_moments(const oracle_params *P, const double *f, double *out)
     free(kw);
     free(rho);
 }
+
+/* Number of threads of the parallel loops (results do not depend on it). */
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int oracle_get_threads(void) { return omp_get_max_threads(); }
 
 /* Exposed pieces for the pin tests. */
 double oracle_second_difference(const double *line, int64_t n, int64_t l, int bc)
