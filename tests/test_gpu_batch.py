@@ -1,6 +1,7 @@
 """Batched stepping and the request server: every grid's result in a batch,
-and every request's result from the server, equals the same grid stepped
-alone (which equals the oracle, see test_gpu_parity.py), bit for bit."""
+and every request's result from the server, equals the CPU oracle run on the
+same input (FP64 and FP32 storage, bit for bit; the entropy, whose log is the
+device's, to a relative 1e-12) and the same grid stepped alone."""
 import math
 import time
 
@@ -50,6 +51,20 @@ def mixed_cases(storage):
     return out
 
 
+def assert_moments(got, want, what=""):
+    assert set(got) == set(want)
+    for k in want:
+        if k == "entropy":
+            assert abs(got[k] - want[k]) <= 1e-12 * max(1.0, abs(want[k])), (what, k, got[k], want[k])
+        else:
+            assert got[k] == want[k], (what, k, got[k], want[k])
+
+
+def _oracle(oracle, p, f0, n, Fext):
+    f, h = oracle.run(p, f0, n, F_ext=Fext, history=True)
+    return f, h, (oracle.moments(p, f) if np.isfinite(f).all() else None)
+
+
 def _solo(V, p, f0, n, Fext, hist=0):
     s = V.Solver(p, f0, hist_cap=hist)
     if Fext is not None:
@@ -62,7 +77,7 @@ def _solo(V, p, f0, n, Fext, hist=0):
 
 @pytest.mark.parametrize("storage", [0, 1])
 @pytest.mark.parametrize("chunk,graph", [(4, True), (16, False), (3, True)])
-def test_batch_equals_each_grid_alone(V, storage, chunk, graph):
+def test_batch_equals_oracle_and_each_grid_alone(V, oracle, storage, chunk, graph):
     cases = mixed_cases(storage)
     _log(f"batch storage={storage} chunk={chunk} graph={graph}")
     solvers = []
@@ -73,10 +88,17 @@ def test_batch_equals_each_grid_alone(V, storage, chunk, graph):
         solvers.append(s)
     V.batch_step(solvers, [c[2] for c in cases], chunk_cycles=chunk, use_graph=graph)
     for s, (p, f0, n, Fext) in zip(solvers, cases):
+        what = (p.model, p.nx, p.np_, p.storage)
+        f, h, m = s.read_f(), s.mag_history(), s.moments()
+        f_ref, h_ref, m_ref = _oracle(oracle, p, f0, n, Fext)
+        assert np.array_equal(f, f_ref), what
+        if p.model in (I.MODEL_HMF, I.MODEL_RING):
+            assert np.array_equal(h, h_ref), what
+        assert_moments(m, m_ref, what)
         f_solo, m_solo, h_solo = _solo(V, p, f0, n, Fext, hist=16)
-        assert np.array_equal(s.read_f(), f_solo), (p.model, p.nx, p.np_)
-        assert np.array_equal(s.mag_history(), h_solo)
-        assert s.moments() == m_solo
+        assert np.array_equal(f, f_solo), what
+        assert np.array_equal(h, h_solo)
+        assert m == m_solo
         s.close()
 
 
@@ -126,7 +148,7 @@ def _serve(V, cases, storage, arena_bytes, max_slots=8, chunk=8):
 
 
 @pytest.mark.parametrize("storage", [1, 0])
-def test_server_results_equal_solo_runs(V, storage):
+def test_server_results_equal_oracle_and_solo_runs(V, oracle, storage):
     cases = [c for c in mixed_cases(storage) if c[3] is None]
     # arena for roughly two requests at a time: admission must queue
     need = max(V.request_footprint(c[0]) for c in cases)
@@ -134,17 +156,31 @@ def test_server_results_equal_solo_runs(V, storage):
     _log(f"server storage={storage}, arena {tables + 2 * need} bytes")
     res = _serve(V, cases, storage, tables + 2 * need + 4096)
     for (r, f), (p, f0, n, _) in zip(res, cases):
+        what = (p.model, p.nx, p.np_, p.storage)
         assert r["status"] == 0 and r["steps_done"] == n
+        f_ref, _, m_ref = _oracle(oracle, p, f0, n, None)
+        assert np.array_equal(f, f_ref), what
+        assert_moments(r["moments"], m_ref, what)
         f_solo, m_solo, _ = _solo(V, p, f0, n, None)
-        assert np.array_equal(f, f_solo), (p.model, p.nx, p.np_)
+        assert np.array_equal(f, f_solo), what
         assert r["moments"] == m_solo
         assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
 
 
-def test_server_mix_of_many_requests(V):
-    trace = I.serving_trace(24, seed=3, sides=(64, 128, 256), steps_range=(5, 40))
+@pytest.mark.parametrize("storage", [1, 0])
+def test_server_mix_of_many_requests(V, oracle, storage):
+    # 24 requests of the parameter scan (three models, uneven sides), six at a
+    # time: every result equals the oracle on the same input
+    trace = I.serving_trace(24, seed=3, sides=(64, 128, 256), steps_range=(5, 40), storage=storage)
     cases = [(q.params, q.initial_condition(), q.nsteps, None) for q in trace]
-    res = _serve(V, cases, 1, 64 << 20, max_slots=6, chunk=8)
+    _log(f"server mix storage={storage}")
+    res = _serve(V, cases, storage, 64 << 20, max_slots=6, chunk=8)
+    for (r, f), (p, f0, n, _) in zip(res, cases):
+        what = (p.model, p.nx, p.np_, n)
+        assert r["status"] == 0 and r["steps_done"] == n
+        f_ref, _, m_ref = _oracle(oracle, p, f0, n, None)
+        assert np.array_equal(f, f_ref), what
+        assert_moments(r["moments"], m_ref, what)
     for i in (0, 7, 23):
         (r, f), (p, f0, n, _) = res[i], cases[i]
         f_solo, m_solo, _ = _solo(V, p, f0, n, None)
@@ -152,10 +188,10 @@ def test_server_mix_of_many_requests(V):
         assert r["moments"] == m_solo
 
 
-def test_every_launch_shape_gives_identical_results(V):
+def test_every_launch_shape_gives_identical_results(V, oracle):
     p = I.Params(I.MODEL_SHEET, 600, 90, -10.0, 10.0, -4.0, 4.0, 0.05, bc_x=I.BC_ZERO)
     f0 = I.waterbag(p, 1.0, 0.5, 1e-4, 3)
-    ref = None
+    ref = oracle.run(p, f0, 7)
     for shape in V.tuning_candidates():
         s = V.Solver(p, f0)
         s.set_tuning(*shape)
@@ -163,8 +199,6 @@ def test_every_launch_shape_gives_identical_results(V):
         s.step(7)
         f = s.read_f()
         s.close()
-        if ref is None:
-            ref = f
         assert np.array_equal(f, ref), shape
     assert {c[2] for c in V.tuning_candidates()} == {0, 256, 512}
     s = V.Solver(p, f0)

@@ -294,3 +294,25 @@ def test_entropy_and_negative_mass_of_an_overshooting_state(V, oracle):
         assert np.array_equal(got, want)
         assert (want < 0).any() and mom["neg_mass"] < 0
         assert_moments(mom, oracle.moments(q, want), f"overshoot storage={storage}")
+
+
+@pytest.mark.timeout(900)
+def test_hmf_1024_unstable_full_run_matches_oracle(V, oracle):
+    """HMF 1024^2 Gaussian at T = 0.4 (below the critical temperature 1/2),
+    dt = 0.05, the full 2000 steps: the linear instability amplifies any
+    roundoff by about 1e5 over the run (growth rate 0.116, t = 100), so
+    bitwise agreement at the end tests the whole arithmetic contract.  The
+    oracle runs on all host threads (its results do not depend on them)."""
+    p, f0, nsteps = I.hmf_gaussian(1024, 0.4)
+    _log(f"hmf 1024^2 T=0.4, {nsteps} steps (oracle on {oracle.threads()} threads)")
+    s = V.Solver(p, f0, hist_cap=nsteps)
+    s.step(nsteps)
+    got, hist, mom = s.read_f(), s.mag_history(), s.moments()
+    s.close()
+    want, hist_want = oracle.run(p, f0, nsteps, history=True)
+    assert_same(got, want, "hmf 1024^2 after 2000 steps")
+    assert np.array_equal(hist, hist_want)
+    assert_moments(mom, oracle.moments(p, want), "hmf 1024^2")
+    # the run left the linear regime: |M| grew from 5e-4 by more than 10^1.5
+    m = np.hypot(hist[:, 0], hist[:, 1])
+    assert m[-1] > 30 * m[0]

@@ -26,17 +26,27 @@ def V():
     return vlasov
 
 
-@pytest.mark.parametrize("n", [256, 512])
+def _one_digit(x: float) -> float:
+    """x rounded to one significant digit (the precision the tables print)."""
+    return float(f"{x:.0e}")
+
+
+@pytest.mark.parametrize("n", [
+    256,
+    pytest.param(512, marks=pytest.mark.xfail(
+        strict=True, reason="Table 2 prints 4e-4 at n = 512; this scheme gives 5.4e-4, the same splitting "
+                            "error as at every other n (a stated discrepancy: the end time of the paper's "
+                            "runs is not given)")),
+])
 def test_table_2_energy_error(V, n):
-    # dt = 0.1, t = 100 (the end time the tables leave unstated): at this dt the
-    # splitting error dominates and the printed 5e-4 (n = 256) and 4e-4
-    # (n = 512) are the same 5.4e-4 within their one digit
+    # dt = 0.1, t = 100 (the end time the tables leave unstated); each printed
+    # value is checked only to its one printed digit
     from paper_1206_3229_amd import conservation as Cn
     printed = json.load(open(GOLDEN))["fd"]["0.1"][str(n)][0]
     p = Cn.sheet_table_params(n, 0.1)
     r = Cn.track(V, p, I.waterbag(p, 1.0, 0.5), 1000, 10)
-    assert 0.9 * printed <= r["delta_e"] < 1.5 * printed, r["delta_e"]
     assert r["delta_norm"] < 1e-4
+    assert _one_digit(r["delta_e"]) == printed, r["delta_e"]
 
 
 @pytest.mark.parametrize("T,rate", [(0.4, 0.116166), (0.6, -0.109956)])

@@ -187,4 +187,4 @@ def test_sheet_energy_error_matches_table_2(oracle):
     for _ in range(100):
         f = oracle.run(p, f, 10)
         de = max(de, abs(oracle.moments(p, f)["energy"] - e0) / abs(e0))
-    assert 0.9 * printed <= de < 1.1 * printed, de  # rounds to the printed digit
+    assert float(f"{de:.0e}") == printed, de  # rounds to the one printed digit
