@@ -82,6 +82,46 @@ def measured_traffic(workload: str, kernel: str, shape):
     return float(m.group(1)) if m else None
 
 
+def traced_launch_us(workload: str, kernel: str, shape):
+    """Average launch duration of `kernel` in the committed rocprofv3 kernel
+    trace (profiles/kernel_trace_<workload>.md), if it was taken on the
+    current kernel sources in the same launch shape; else None."""
+    path = os.path.join(ROOT, "profiles", f"kernel_trace_{workload}.md")
+    if not os.path.exists(path) or not shape:
+        return None
+    text = open(path).read()
+    m = re.search(r"^kernel_source_hash: (\S+)$", text, re.M)
+    sh = re.search(r"^launch_shape: (\S+)$", text, re.M)
+    if not m or m.group(1) != kernel_source_hash() or not sh or sh.group(1) != shape_str(shape):
+        return None
+    m = re.search(rf"^\| {re.escape(kernel)} \| [^|]* \| (\d+) \| ([0-9.]+) \|", text, re.M)
+    return float(m.group(2)) if m else None
+
+
+def fp32_error_vs_fp64(torch, V, w64: str, w32: str, shape64, shape32) -> dict:
+    """Diagnostics and f of the FP32-storage run against the FP64 run after the
+    workload's full number of steps, both from the same initial condition."""
+    out = {}
+    res = {}
+    for key, w, shape in (("f64", w64, shape64), ("f32", w32, shape32)):
+        p, f0, nsteps = WORKLOADS[w]()
+        s = V.Solver(p, f0)
+        if shape:
+            s.set_tuning(*shape)
+        s.step(nsteps)
+        res[key] = (s.moments(), s.read_f())
+        s.close()
+        out["steps"] = nsteps
+    (m64, f64), (m32, f32) = res["f64"], res["f32"]
+    out["energy_rel"] = abs(m32["energy"] - m64["energy"]) / abs(m64["energy"])
+    out["mass_abs"] = abs(m32["mass"] - m64["mass"])
+    out["momentum_abs"] = abs(m32["momentum"] - m64["momentum"])
+    out["magnetization_abs"] = math.hypot(m32["mx"] - m64["mx"], m32["my"] - m64["my"])
+    out["l2_rel"] = abs(m32["l2"] - m64["l2"]) / abs(m64["l2"])
+    out["f_rel_max"] = float(np.max(np.abs(f32 - f64)) / np.max(np.abs(f64)))
+    return out
+
+
 def copy_ceiling(torch, V, nbytes=1 << 30, reps=20):
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -128,19 +168,57 @@ def run_gpu(workload: str, steps: int, warmup: int, torch, V, tuning=None):
     return p, (t1 - t0), prof, m, (t3 - t2)
 
 
-def cpu_baseline(workload: str, seconds_target: float = 15.0):
-    """The CPU oracle, as it stands, on a bounded sample of the same workload."""
-    from oracle import oracle as O
-    p, f0, _ = WORKLOADS[workload]()
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Threads the oracle may use here: OMP_NUM_THREADS if set, else the CPUs
+    this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def _oracle_rate(O, p, f, threads: int, seconds: float):
+    """Updates/s of the oracle on `threads` threads: one untimed step, then
+    as many whole steps as fill about `seconds` (at most 50)."""
+    O.set_threads(threads)
     t0 = time.perf_counter()
-    f = O.run(p, f0, 1)
+    f = O.run(p, f, 1)
     one = time.perf_counter() - t0
-    nsteps = max(1, min(20, int(seconds_target / max(one, 1e-3))))
+    nsteps = max(1, min(50, int(seconds / max(one, 1e-3))))
     t0 = time.perf_counter()
     O.run(p, f, nsteps)
     el = time.perf_counter() - t0
-    return {"value": p.nx * p.np_ * nsteps / el, "unit": "grid-point updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nsteps} time steps of {workload} (single-threaded plain C oracle, after one untimed step)"}
+    return p.nx * p.np_ * nsteps / el, nsteps, el
+
+
+def cpu_baseline(workload: str, seconds_per_leg: float = 8.0):
+    """The CPU oracle, as it stands, on a bounded sample of the same workload:
+    all host threads (the value), and one thread."""
+    from oracle import oracle as O
+    p, f0, _ = WORKLOADS[workload]()
+    n = host_threads()
+    v_all, s_all, t_all = _oracle_rate(O, p, f0, n, seconds_per_leg)
+    v_one, s_one, t_one = _oracle_rate(O, p, f0, 1, seconds_per_leg)
+    O.set_threads(n)
+    return {"value": v_all, "unit": "grid-point updates/s", "cores": n, "kind": "oracle",
+            "sample": f"{s_all} time steps of {workload} on {n} threads ({t_all:.1f} s, after one untimed step); "
+                      f"the plain C oracle, OpenMP over lines, results independent of the thread count",
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": v_one, "steps": s_one, "seconds": t_one},
+            "thread_speedup": v_all / v_one}
 
 
 # ---------------------------------------------------------------------------
@@ -205,7 +283,10 @@ def run_server(V, trace, ics, arrivals, keep, arena_bytes, max_slots, chunk):
 
 def serving(V, torch, nreq, seed=0, arena_bytes=2 << 30, max_slots=48, chunk=16):
     trace = I.serving_trace(nreq, rate=math.inf, seed=seed, storage=I.STORAGE_F32)
-    ics = [q.initial_condition() for q in trace]
+    # each request carries its initial-condition spec (U, M0, noise, seed); the
+    # server, and the sequential baseline, build f0 on the device inside the
+    # measured time
+    ics = [V.ic_waterbag_um(q.U, q.M0, 1e-4, q.seed) for q in trace]
     work = [q.params.nx * q.params.np_ * q.nsteps for q in trace]
     keep = set(range(0, nreq, 32))
     seq = run_sequential_fp64(V, torch, trace, ics, keep)
@@ -258,6 +339,19 @@ def serving(V, torch, nreq, seed=0, arena_bytes=2 << 30, max_slots=48, chunk=16)
         "speedup_vs_sequential_fp64": (total / span) / (total / t_seq),
         "accuracy_vs_fp64": accuracy,
     }
+
+
+def model_leg(V, torch, workload: str, steps: int, warmup: int, shape) -> dict:
+    """Another model at full size beside the headline: throughput, the kernel
+    times (a second, profiled run) and the per-step time outside the fused
+    kernel."""
+    p, secs, prof, _, _ = run_gpu(workload, steps, warmup, torch, V, shape)
+    us = {k: (v[0] / v[1] * 1e3 if v[1] else None) for k, v in prof.items()}
+    ms = secs / steps * 1e3
+    kd = us.get("kick_drift2")
+    return {"workload": workload, "value": p.nx * p.np_ * steps / secs, "unit": "grid-point updates/s",
+            "ms_per_step": ms, "steps": steps, "kernels_us": us,
+            "outside_fused_kernel_us_per_step": (ms * 1e3 - kd) if kd else None}
 
 
 def variant_rate(V, torch, workload: str, steps: int, shape, **overrides) -> dict:
@@ -331,6 +425,9 @@ def main():
     bpp = algorithmic_bytes_per_point(dom, s_bytes)
     achieved = bpp * npts / avg_s / 1e9
     traffic = measured_traffic(args.workload, dom, shape) if shape else None
+    trace_us = traced_launch_us(args.workload, dom, shape)
+    ms_step = secs / args.steps * 1e3
+    sweeps_bpp = 6 * s_bytes + 8.0 / 16.0
     out = {
         "metric": "grid-point updates/s per Strang step",
         "value": value,
@@ -338,7 +435,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": secs / args.steps * 1e3,
+        "ms_per_step": ms_step,
         "ms_per_step_with_kernel_events": secs_events / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -349,8 +446,18 @@ def main():
                    "x": [p.xmin, p.xmax], "p": [p.pmin, p.pmax], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "bytes_per_point": bpp, "avg_launch_us": avg_s * 1e6, "launches": dom_n},
+                     "bytes_per_point": bpp, "avg_launch_us": avg_s * 1e6, "launches": dom_n,
+                     "trace_avg_launch_us": trace_us,
+                     "frac_trace": (bpp * npts / (trace_us * 1e-6) / 1e9 / HBM_PEAK_GBPS) if trace_us else None,
+                     "three_sweep_bytes_per_update": sweeps_bpp,
+                     "three_sweep_equivalent_GBps": sweeps_bpp * npts / (ms_step * 1e-3) / 1e9,
+                     "note": ("bytes_per_point counts what the fused kernel moves: the kick and both half drifts "
+                              "read f once and write it once (2s bytes) plus one FP64 density partial per 16 rows; "
+                              "three separate sweeps would move 6s + 0.5 bytes per update, the figure "
+                              "three_sweep_equivalent_GBps applies to the whole step")},
         "kernels_us": {k: (v[0] / v[1] * 1e3 if v[1] else None) for k, v in prof.items()},
+        "outside_fused_kernel_us_per_step": (ms_step * 1e3 - prof["kick_drift2"][0] / prof["kick_drift2"][1] * 1e3
+                                             if prof.get("kick_drift2", (0, 0))[1] else None),
         "launch_shape": {"drift_threads": shape[0], "kick_rows": shape[1], "kick_drift_width": shape[2],
                          "kick_drift_blocks": shape[3],
                          "autotune_us_per_step": {
@@ -370,7 +477,9 @@ def main():
                                    "launch_shape": shape32,
                                    "ms_per_step": secs32 / args.steps * 1e3,
                                    "kernels_us": {k: (v[0] / v[1] * 1e3 if v[1] else None)
-                                                  for k, v in prof32.items()}}
+                                                  for k, v in prof32.items()},
+                                   "error_vs_fp64": fp32_error_vs_fp64(torch, V, args.workload, alt, shape,
+                                                                       shape32)}
     if not (args.no_extras or args.no_variants):
         steps_v = max(2, args.steps // 10)
         # the paper's baseline interpolation (global spline, eq. tridiagsys) on the same workload
@@ -379,6 +488,10 @@ def main():
         out["triple_jump"] = variant_rate(V, torch, args.workload, steps_v, shape, splitting=I.SPLIT_TRIPLE_JUMP)
         out["filter_every_step"] = variant_rate(V, torch, args.workload, steps_v, shape, filter_every=1,
                                                 filter_strength=1.0)
+    if not (args.no_extras or args.no_variants):
+        # the other two models at their full sizes (per-step overhead beside the headline)
+        out["other_models"] = [model_leg(V, torch, w, max(2, args.steps // 10), 5, shape)
+                               for w in ("hmf_gaussian_2048x2048_T0.4_f64", "ring_2048x2048_f64")]
     if not args.no_copy:
         out["copy_ceiling_GBps"] = copy_ceiling(torch, V)
     if args.no_extras:

@@ -143,7 +143,8 @@ size_t vlasov_f_bytes(const vlasov_params *p);
 size_t vlasov_workspace_bytes(const vlasov_params *p);
 
 /* Create a context.  f0_host: nx*np FP64 values, row-major [np][nx], copied
- * (rounded to nearest FP32 for F32 storage).  f_dev: vlasov_f_bytes() bytes;
+ * (rounded to nearest FP32 for F32 storage); NULL leaves f unset (then
+ * vlasov_generate_ic or vlasov_write_f gives it).  f_dev: vlasov_f_bytes() bytes;
  * ws_dev: vlasov_workspace_bytes() bytes.  Builds the drift line tables
  * (constant over the run) and the model tables on the host and uploads them.
  * Synchronises hip_stream before returning.  Errors: VLASOV_E_INVAL for bad
@@ -160,6 +161,16 @@ int vlasov_set_external_force(vlasov_ctx *c, const double *F_host);
  * Consecutive half drifts of successive (sub)steps are fused into one pass
  * over f; the result is bit-identical to nsteps separate steps. */
 int vlasov_step(vlasov_ctx *c, int64_t nsteps);
+
+/* Steps that are not the last of a vlasov_step call are enqueued
+ * steps_per_graph at a time as one HIP graph launch (default 0: every kernel
+ * launched on its own, which measured faster on the 4096^2 sheet).  The graph of a context is captured the first
+ * time it is needed (once for each of the two buffers f may start in) and
+ * replayed afterwards; its kernels are those of the eager path, so results are
+ * identical bit for bit.  Graphs are not used while the per-kernel timers are
+ * on or with the filter.  Synchronises the stream when the value changes;
+ * VLASOV_E_INVAL outside [0, 4096]. */
+int vlasov_set_graph(vlasov_ctx *c, int32_t steps_per_graph);
 
 /* The individual sweeps of a step, for inspection and testing (with the
  * sizes of the first substep: dt itself for the Strang splitting).
@@ -191,6 +202,46 @@ int vlasov_read_f(vlasov_ctx *c, double *f_host);
 /* Replace the current f (checkpoint restore), FP64 [np][nx]; synchronises.
  * The step count of the filter schedule is not changed. */
 int vlasov_write_f(vlasov_ctx *c, const double *f_host);
+
+/* Initial conditions the library generates on the device (the paper's
+ * workloads, Sec. 4), every one normalised to unit mass on the grid: the raw
+ * values r_ij are summed in index order (each row from i = 0, then the row
+ * sums from j = 0) to S, and f_ij = r_ij / ((S dx) dp) (rounded to FP32 for F32
+ * storage).  Nodes u_k = umin + k du.
+ *   WATERBAG     r = 1 on |x_i| <= a0, |p_j| <= a1 (inclusive; each half-width
+ *                raised to at least two cells), else 0; with amp != 0 the
+ *                support values are 1 + amp eta_k, eta_k = 2 u_k - 1, u_k the
+ *                top 53 bits of output k = j nx + i of the SplitMix64 stream of
+ *                `seed` (Steele, Lea and Flood 2014: z = seed + (k + 1)
+ *                0x9E3779B97F4A7C15, then the mix with shifts 30, 27, 31 and
+ *                multipliers 0xBF58476D1CE4E5B9, 0x94D049BB133111EB) times 2^-53.
+ *   WATERBAG_UM  the HMF waterbag of magnetization M0 = a1 in [0, 1) and energy
+ *                per particle U = a0 (Sec. 4.2): theta0 solves sin(t)/t = M0
+ *                (bisection on (0, pi), at most 200 halvings, until hi - lo <=
+ *                4e-16 hi; theta0 the midpoint), p0 = sqrt(6 (U - (1 - M0^2)/2));
+ *                then WATERBAG with half-widths (theta0, p0).
+ *   GAUSSIAN     r = exp(-p_j^2 / (2 a0)) (1 + amp cos(x_i - phi)) with a0 = T > 0,
+ *                |amp| < 1, phi = 0 for seed 0, else 2 pi u_0; exp and cos are
+ *                the host C library's, evaluated once per node. */
+typedef enum {
+    VLASOV_IC_HOST = 0,  /* f0 comes from the caller (requests only) */
+    VLASOV_IC_WATERBAG = 1,
+    VLASOV_IC_WATERBAG_UM = 2,
+    VLASOV_IC_GAUSSIAN = 3
+} vlasov_ic_kind;
+
+typedef struct {
+    int32_t kind;  /* vlasov_ic_kind */
+    int32_t reserved;
+    double a0, a1, amp;
+    uint64_t seed;
+} vlasov_ic;
+
+/* Replace the current f by a generated initial condition (device kernels on
+ * the context's stream); synchronises.  VLASOV_E_INVAL for an unknown kind or
+ * parameters outside the ranges above (checked before anything runs), or if
+ * the raw values sum to zero (no node in the support; f is then undefined). */
+int vlasov_generate_ic(vlasov_ctx *c, const vlasov_ic *ic);
 
 /* Release the context (host memory only; caller device memory is untouched).
  * Synchronises the stream first. */
@@ -267,6 +318,9 @@ typedef struct {
     int64_t nsteps;   /* >= 0 */
     int32_t keep_f;   /* nonzero: keep the final f for vlasov_poll */
     int32_t reserved;
+    vlasov_ic ic;     /* kind VLASOV_IC_HOST: f0 passed to vlasov_submit; any other
+                         kind: generated by the server on the device when the
+                         request is admitted (part of its latency) */
 } vlasov_request;
 
 typedef struct {
@@ -292,8 +346,10 @@ int vlasov_server_create(void *arena_dev, size_t arena_bytes, void *hip_stream, 
                          int32_t chunk_cycles, int32_t use_graph, vlasov_server **out);
 
 /* Queue a request (thread-safe, non-blocking).  f0_host: [np][nx] FP64,
- * copied.  VLASOV_E_INVAL for invalid parameters, VLASOV_E_NOMEM if the
- * footprint exceeds the whole arena, VLASOV_E_STATE after destroy began. */
+ * copied, for r->ic.kind == VLASOV_IC_HOST; ignored (may be NULL) otherwise.
+ * VLASOV_E_INVAL for invalid parameters or initial-condition spec,
+ * VLASOV_E_NOMEM if the footprint exceeds the whole arena, VLASOV_E_STATE after
+ * destroy began. */
 int vlasov_submit(vlasov_server *s, const vlasov_request *r, const double *f0_host, uint64_t *ticket);
 
 /* VLASOV_PENDING while queued or running; VLASOV_OK once done: writes the

@@ -7,9 +7,9 @@ namespace vlasov_detail {
 template <typename T, int TW, int RB>
 int launch_kick_drift_t(vlasov_ctx *c, int ta, double h)
 {
-    // whole wavefronts, about 5/8 TW threads: one first-pass run and up to two
-    // kicked columns per thread
-    constexpr int NT = (TW / 8 * 5 + 63) / 64 * 64;
+    // one kicked column per thread (whole wavefronts); the two half drifts
+    // run on waves of their own
+    constexpr int NT = vk::KDGeom<TW>::NT;
     const vlasov_params &P = c->P;
     const int ntx = (int)((P.nx + TW - 1) / TW), nty = (int)((c->nblk + RB - 1) / RB);
     const dim3 grid((unsigned)vk::xcd_grid(ntx, nty));
@@ -17,15 +17,15 @@ int launch_kick_drift_t(vlasov_ctx *c, int ta, double h)
     T *fout = (T *)c->fnext();
     const double *F = force_ptr(c);
     const int tb = (ta + 1) % c->nsub;
-    const int32_t *dm1 = c->dm(ta), *dm2 = c->dm(tb);
+    const int32_t *dm2 = c->dm(tb);
     const double4 *dw1 = c->dw(ta), *dw2 = c->dw(tb);
     const int32_t *kbase = c->at<int32_t>(c->L.kd_base) + (size_t)ta * (size_t)c->nblk;
     const int32_t *krel = c->at<int32_t>(c->L.kd_rel) + (size_t)ta * (size_t)P.np;
     double *part = c->at<double>(c->L.part);
     const int nx = (int)P.nx, np = (int)P.np;
-#define KD_LAUNCH(BX, BP)                                                                                            \
-    launch(c, VLASOV_K_KICK_DRIFT2, vk::k_kick_drift<T, 2, BX, BP, true, NT, TW, kd_pf<T>(), RB>, grid, dim3(NT), fin,  \
-           fout, F, h, c->dp, dm1, dw1, dm2, dw2, kbase, krel, part, nx, np, ntx, nty)
+#define KD_LAUNCH(BX, BP)                                                                                        \
+    launch(c, VLASOV_K_KICK_DRIFT2, vk::k_kick_drift<T, BX, BP, TW, kd_pf<T>(), RB>, grid, dim3(NT), fin, fout, F, \
+           h, c->dp, dm2, dw1, dw2, kbase, krel, part, nx, np, ntx, nty)
     if (P.bc_x == VLASOV_BC_PERIODIC) {
         if (P.bc_p == VLASOV_BC_PERIODIC) KD_LAUNCH(vk::BC_PERIODIC, vk::BC_PERIODIC); else KD_LAUNCH(vk::BC_PERIODIC, vk::BC_ZERO);
     } else {

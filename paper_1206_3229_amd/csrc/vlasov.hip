@@ -293,6 +293,73 @@ int upload_f(vlasov_ctx *c, const double *f_host)
     return VLASOV_OK;
 }
 
+// Steps 2-4 of one (sub)step sequence and step 1 of the next: the body of a
+// step that is not the last of a call (more = true), or of the last one.
+int step_body(vlasov_ctx *c, bool more)
+{
+    const int every = c->P.filter_every;
+    const bool filtered = every > 0 && (c->steps_done + 1) % every == 0;
+    int rc = VLASOV_OK;
+    for (int k = 0; rc == VLASOV_OK && k < c->nsub; ++k) {
+        rc = density_force(c);  // step 2
+        // step 3 (+ the filter after the last kick of a filtered step),
+        // step 4, and step 1 of the next substep (or step)
+        const bool last = k + 1 == c->nsub;
+        const int tb = !last ? k + 1 : (more ? 0 : -1);
+        if (rc == VLASOV_OK) rc = kick_then_drift(c, k, tb, c->wsub[k] * c->P.dt, filtered && last);
+    }
+    if (rc == VLASOV_OK) ++c->steps_done;
+    return rc;
+}
+
+void drop_graphs(vlasov_ctx *c)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        c->gexec[k] = nullptr;
+    }
+}
+
+// gsteps steps that are not the last of a call, as one graph launch: the
+// graph for the current buffer is captured (on a private stream; the host
+// state advances as the capture enqueues) and then replayed with the host
+// state advanced by hand.  The sequence of kernels of such a step depends
+// only on the current buffer (no filter schedule: graphs are not used with
+// the filter).
+int graph_steps(vlasov_ctx *c)
+{
+    const int start = c->cur;
+    if (!c->gexec[start]) {
+        if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipStream_t user = c->stream;
+        c->stream = c->cap_stream;
+        hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+        int rc = e == hipSuccess ? VLASOV_OK : fail(VLASOV_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+        const int64_t done0 = c->steps_done;
+        for (int s = 0; rc == VLASOV_OK && s < c->gsteps; ++s) rc = step_body(c, true);
+        hipGraph_t g = nullptr;
+        if (e == hipSuccess) e = hipStreamEndCapture(c->cap_stream, &g);
+        c->stream = user;
+        c->steps_done = done0;
+        if (rc == VLASOV_OK && e != hipSuccess) rc = fail(VLASOV_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+        if (rc == VLASOV_OK) {
+            e = hipGraphInstantiate(&c->gexec[start], g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                c->gexec[start] = nullptr;
+                rc = fail(VLASOV_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+            }
+        }
+        if (g) (void)hipGraphDestroy(g);
+        if (rc != VLASOV_OK) return rc;
+        c->gcur_end[start] = c->cur;
+    }
+    HIP_TRY(hipGraphLaunch(c->gexec[start], c->stream));
+    c->cur = c->gcur_end[start];
+    c->have_force = true;
+    c->steps_done += c->gsteps;
+    return VLASOV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -316,7 +383,7 @@ int vlasov_init(const vlasov_params *p, const double *f0_host, void *f_dev, void
 {
     std::string why = validate(p);
     if (!why.empty()) return fail(VLASOV_E_INVAL, why);
-    if (!f0_host || !f_dev || !ws_dev || !out) return fail(VLASOV_E_INVAL, "NULL pointer argument");
+    if (!f_dev || !ws_dev || !out) return fail(VLASOV_E_INVAL, "NULL pointer argument");
     if (((uintptr_t)f_dev % ALIGN) || ((uintptr_t)ws_dev % ALIGN))
         return fail(VLASOV_E_INVAL, "device buffers must be 256-byte aligned");
     vlasov_ctx *c = new vlasov_ctx();
@@ -428,7 +495,11 @@ int vlasov_init(const vlasov_params *p, const double *f0_host, void *f_dev, void
         hipMemsetAsync(c->ws + c->L.hcount, 0, sizeof(int64_t), c->stream) != hipSuccess ||
         hipMemsetAsync(c->ws + c->L.mxmy, 0, 2 * sizeof(double), c->stream) != hipSuccess)
         return cleanup_fail(fail(VLASOV_E_HIP, "workspace clear failed"));
-    if ((rc = upload_f(c, f0_host)) != VLASOV_OK) return cleanup_fail(rc);
+    if (f0_host) {
+        if ((rc = upload_f(c, f0_host)) != VLASOV_OK) return cleanup_fail(rc);
+    } else if (hipStreamSynchronize(c->stream) != hipSuccess) {  // the host tables above are locals
+        return cleanup_fail(fail(VLASOV_E_HIP, "table upload failed"));
+    }
     *out = c;
     return VLASOV_OK;
 }
@@ -448,21 +519,30 @@ int vlasov_step(vlasov_ctx *c, int64_t nsteps)
     if (!c) return fail(VLASOV_E_INVAL, "NULL context");
     if (nsteps < 0) return fail(VLASOV_E_INVAL, "nsteps must be >= 0");
     if (nsteps == 0) return VLASOV_OK;
-    const int every = c->P.filter_every;
     int rc = drift(c, 0, -1, true);  // step 1 of the first (sub)step
-    for (int64_t s = 0; rc == VLASOV_OK && s < nsteps; ++s) {
-        const bool filtered = every > 0 && (c->steps_done + 1) % every == 0;
-        for (int k = 0; rc == VLASOV_OK && k < c->nsub; ++k) {
-            rc = density_force(c);  // step 2
-            // step 3 (+ the filter after the last kick of a filtered step),
-            // step 4, and step 1 of the next substep (or step)
-            const bool last = k + 1 == c->nsub;
-            const int tb = !last ? k + 1 : (s + 1 < nsteps ? 0 : -1);
-            if (rc == VLASOV_OK) rc = kick_then_drift(c, k, tb, c->wsub[k] * c->P.dt, filtered && last);
-        }
-        if (rc == VLASOV_OK) ++c->steps_done;
+    int64_t s = 0;
+    // steps before the last one, gsteps at a time from a graph (not while
+    // per-kernel timers are on, nor with the filter, whose schedule depends
+    // on the step count)
+    const bool graphs = c->gsteps > 0 && !c->prof && c->P.filter_every == 0;
+    while (graphs && rc == VLASOV_OK && nsteps - 1 - s >= c->gsteps) {
+        rc = graph_steps(c);
+        s += c->gsteps;
     }
+    for (; rc == VLASOV_OK && s < nsteps; ++s) rc = step_body(c, s + 1 < nsteps);
     return rc;
+}
+
+int vlasov_set_graph(vlasov_ctx *c, int32_t steps_per_graph)
+{
+    if (!c) return fail(VLASOV_E_INVAL, "NULL context");
+    if (steps_per_graph < 0 || steps_per_graph > 4096) return fail(VLASOV_E_INVAL, "steps_per_graph must be in [0, 4096]");
+    if (steps_per_graph != c->gsteps) {
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        drop_graphs(c);
+        c->gsteps = steps_per_graph;
+    }
+    return VLASOV_OK;
 }
 
 int vlasov_drift(vlasov_ctx *c, int32_t npass)
@@ -620,6 +700,8 @@ int vlasov_destroy(vlasov_ctx *c)
         (void)hipEventDestroy(r.b);
     }
     for (auto e : c->pool) (void)hipEventDestroy(e);
+    drop_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return VLASOV_OK;
 }
@@ -655,6 +737,8 @@ int vlasov_set_tuning(vlasov_ctx *c, const vlasov_tuning *t)
     const bool b_ok = t->kick_drift_blocks == 1 || t->kick_drift_blocks == 2 || t->kick_drift_blocks == 4;
     if (!nt_ok || !r_ok || !w_ok || !b_ok) return fail(VLASOV_E_INVAL, "launch shape not compiled in");
     const bool retable = t->kick_drift_blocks != c->kd_rb;
+    HIP_TRY(hipStreamSynchronize(c->stream));  // the graphs of the old shape may still run
+    drop_graphs(c);
     c->tune = *t;
     if (retable) {
         HIP_TRY(hipStreamSynchronize(c->stream));  // no kernel may read the tables being replaced

@@ -6,6 +6,7 @@
 // every later cycle closes step s and opens step s + 1 with the fused pair of
 // half drifts; the last cycle closes the last step with a single half drift.
 // Cycles that open a step also run the density, force and kick of that step.
+#include <stdlib.h>
 #include <string.h>
 
 #include <chrono>
@@ -23,7 +24,7 @@ using namespace vlasov_detail;
 namespace {
 
 // Persistent launch widths (workgroups) of the four batched phases.
-constexpr int KB_DRIFT_WG = 2048, KB_DENS_WG = 1024, KB_FORCE_WG = 256, KB_KICK_WG = 2048;
+constexpr int KB_DRIFT_WG = 2048, KB_DENS_WG = 1024, KB_FORCE_WG = 256, KB_KICK_WG = 2048, KB_KD_WG = 1024;
 constexpr int KB_FORCE_NT = 1024;
 
 size_t set_bytes(int K) { return align_up(sizeof(vk::GridDesc) * vk::BATCH_MAX + sizeof(vk::Cycle) * (size_t)K); }
@@ -31,8 +32,21 @@ size_t set_bytes(int K) { return align_up(sizeof(vk::GridDesc) * vk::BATCH_MAX +
 struct Member {
     vlasov_ctx *c;
     int64_t total, started, closed;
+    // the open step has its first half drift but not yet its kick (after a
+    // fused kick and drift pair)
+    bool half_open = false;
     bool done() const { return closed == total; }
 };
+
+// The fused kick and drift pair runs on a member whose drift offsets vary
+// little enough inside its 16-row tiles (tables built for one block per
+// tile) and whose p axis is periodic.
+bool fusable(const vlasov_ctx *c)
+{
+    return c->kd_ok[0] && c->kd_rb == 1 && c->P.bc_p == VLASOV_BC_PERIODIC;
+}
+
+int kd_tiles(const vlasov_ctx *c) { return (int)((c->P.nx + 255) / 256) * (int)c->nblk; }
 
 int drift_tiles(const vlasov_ctx *c)
 {
@@ -87,6 +101,8 @@ vk::GridDesc describe(const vlasov_ctx *c)
     g.dp = c->dp;
     g.dt = c->P.dt;
     g.sheetK = ((2.0 * M_PI) * c->P.sheet_G) * c->dx;
+    g.kbase = c->at<int32_t>(c->L.kd_base);
+    g.krel = c->at<int32_t>(c->L.kd_rel);
     return g;
 }
 
@@ -142,16 +158,21 @@ class Engine {
         for (int k = 0; k < K_; ++k) {
             vk::Cycle &cy = hc[k];
             cy.n = n;
-            cy.off_drift[0] = cy.off_dens[0] = cy.off_force[0] = cy.off_kick[0] = 0;
+            cy.off_drift[0] = cy.off_dens[0] = cy.off_force[0] = cy.off_kick[0] = cy.off_kd[0] = 0;
             for (int a = 0; a < n; ++a) {
                 Member &m = *ms[a];
                 vlasov_ctx *c = m.c;
-                int kind = vk::DRIFT_NONE, kick = 0;
+                // drift phase: the first half drift of the first step, the
+                // pair closing one step and opening the next, or the last
+                // half drift; none when the open step has its first half drift
+                int kind = vk::DRIFT_NONE, kick = 0, fused = 0;
                 if (!m.done()) {
                     if (m.started == m.closed) {
                         kind = vk::DRIFT_FIRST;
                         kick = 1;
                         ++m.started;
+                    } else if (m.half_open) {
+                        kick = 1;
                     } else if (m.started < m.total) {
                         kind = vk::DRIFT_PAIR;
                         kick = 1;
@@ -161,15 +182,25 @@ class Engine {
                         kind = vk::DRIFT_LAST;
                         ++m.closed;
                     }
+                    // kick phase: with a next step to open, the fused kick and
+                    // drift pair where the member allows it
+                    if (kick && fuse_ && m.started < m.total && fusable(c)) {
+                        fused = 1;
+                        ++m.closed;
+                        ++m.started;
+                    }
+                    m.half_open = fused != 0;
                 }
                 cy.slot[a] = a;
                 cy.drift[a] = (int8_t)kind;
                 cy.kick[a] = (int8_t)kick;
                 cy.cur[a] = (int8_t)c->cur;
+                cy.kin[a] = (int8_t)(c->cur ^ (kind ? 1 : 0));
                 cy.off_drift[a + 1] = cy.off_drift[a] + (kind ? drift_tiles(c) : 0);
                 cy.off_dens[a + 1] = cy.off_dens[a] + (kick ? (int)((c->P.nx + 15) / 16) : 0);
                 cy.off_force[a + 1] = cy.off_force[a] + (kick ? force_items(c) : 0);
-                cy.off_kick[a + 1] = cy.off_kick[a] + (kick ? kick_tiles(c) : 0);
+                cy.off_kick[a + 1] = cy.off_kick[a] + (kick && !fused ? kick_tiles(c) : 0);
+                cy.off_kd[a + 1] = cy.off_kd[a] + (fused ? kd_tiles(c) : 0);
                 if (kind) c->cur ^= 1;
                 if (kick) {
                     c->cur ^= 1;
@@ -177,6 +208,8 @@ class Engine {
                 }
             }
         }
+        if (fail_at_ >= 0 && chunks_++ == fail_at_)
+            return fail(VLASOV_E_HIP, "injected failure of a chunk (VLASOV_TEST_FAIL_CHUNK)");
         char *dset = dev_ + (size_t)set * set_bytes(K_);
         HIP_TRY(hipMemcpyAsync(dset, host_[set], set_bytes(K_), hipMemcpyHostToDevice, st_));
         HIP_TRY(hipEventRecord(ev_[set], st_));
@@ -210,6 +243,7 @@ class Engine {
             vk::kb_density<<<KB_DENS_WG, 256, 0, st>>>(gd, cy + k);
             vk::kb_force<<<KB_FORCE_WG, KB_FORCE_NT, 0, st>>>(gd, cy + k);
             vk::kb_kick<T, kick_rows<T>()><<<KB_KICK_WG, 256, 0, st>>>(gd, cy + k);
+            if (fuse_) vk::kb_kick_drift<T, kd_pf<T>()><<<KB_KD_WG, vk::KDGeom<256>::NT, 0, st>>>(gd, cy + k);
         }
     }
 
@@ -233,6 +267,12 @@ class Engine {
     hipGraphExec_t exec_[2] = {nullptr, nullptr};
     hipStream_t cap_ = nullptr;
     int set_ = 0;
+    bool fuse_ = true;  // the fused kick and drift pair for the members that allow it
+
+  public:
+    // failure handling tests: the chunk with this index (from 0) fails after
+    // its planning, before anything is enqueued (-1: never)
+    int64_t fail_at_ = -1, chunks_ = 0;
 };
 
 double seconds_since(std::chrono::steady_clock::time_point t0)
@@ -271,6 +311,8 @@ struct vlasov_server {
         Member m;
         bool keep_f;
         double t_submit, t_admit;
+        int32_t failed = VLASOV_OK;  // error of the chunk this request was in
+        int64_t closed_before = 0;   // steps finished before the current chunk
     };
 
     std::mutex mu;
@@ -350,7 +392,13 @@ void admit(vlasov_server *s)
         }
         const size_t fb = vlasov_f_bytes(&p.req.p);
         vlasov_ctx *c = nullptr;
-        int rc = vlasov_init(&p.req.p, p.f0.data(), s->arena + off, s->arena + off + align_up(fb), s->stream, &c);
+        const bool gen = p.req.ic.kind != VLASOV_IC_HOST;
+        int rc = vlasov_init(&p.req.p, gen ? nullptr : p.f0.data(), s->arena + off, s->arena + off + align_up(fb),
+                             s->stream, &c);
+        if (rc == VLASOV_OK && gen && (rc = vlasov_generate_ic(c, &p.req.ic)) != VLASOV_OK) {
+            vlasov_destroy(c);
+            c = nullptr;
+        }
         const double t_admit = seconds_since(s->t0);
         if (rc != VLASOV_OK) {
             vlasov_result r{};
@@ -388,10 +436,17 @@ void retire(vlasov_server *s)
             continue;
         }
         vlasov_result r{};
-        r.status = vlasov_moments(a.ctx, &r.m);
-        r.steps_done = a.m.closed;
         std::vector<double> f;
-        if (a.keep_f) {
+        if (a.failed != VLASOV_OK) {
+            // the chunk's kernels may not have run (planning already moved the
+            // context to its output buffer): no diagnostics, no f
+            r.status = a.failed;
+            r.steps_done = a.closed_before;
+        } else {
+            r.status = vlasov_moments(a.ctx, &r.m);
+            r.steps_done = a.m.closed;
+        }
+        if (a.keep_f && a.failed == VLASOV_OK) {
             f.resize((size_t)a.ctx->P.nx * (size_t)a.ctx->P.np);
             int rc = vlasov_read_f(a.ctx, f.data());
             if (rc != VLASOV_OK && r.status == VLASOV_OK) r.status = rc;
@@ -450,12 +505,21 @@ void vlasov_server::run()
             continue;
         }
         std::vector<Member *> ms;
-        for (auto &a : active) ms.push_back(&a.m);
+        for (auto &a : active) {
+            a.closed_before = a.m.closed;
+            ms.push_back(&a.m);
+        }
         int rc = eng.chunk(ms);
-        if (rc == VLASOV_OK) rc = hipStreamSynchronize(stream) == hipSuccess ? VLASOV_OK : VLASOV_E_HIP;
+        if (rc == VLASOV_OK) {
+            const hipError_t e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) rc = fail(VLASOV_E_HIP, std::string("chunk: ") + hipGetErrorString(e));
+        }
         if (rc != VLASOV_OK) {
-            // a device error: fail the running requests
-            for (auto &a : active) a.m.closed = a.m.total;
+            // the running requests fail with the chunk's error and leave
+            for (auto &a : active) {
+                a.failed = rc;
+                a.m.closed = a.m.total;
+            }
         }
         retire(this);
     }
@@ -537,6 +601,7 @@ int vlasov_server_create(void *arena_dev, size_t arena_bytes, void *hip_stream, 
     s->max_slots = max_slots;
     s->K = chunk_cycles;
     s->graph = use_graph != 0;
+    if (const char *v = getenv("VLASOV_TEST_FAIL_CHUNK")) s->eng.fail_at_ = strtoll(v, nullptr, 10);
     s->t0 = std::chrono::steady_clock::now();
     s->free_[tb] = (arena_bytes - tb) / ALIGN * ALIGN;
     s->th = std::thread([s] { s->run(); });
@@ -546,7 +611,13 @@ int vlasov_server_create(void *arena_dev, size_t arena_bytes, void *hip_stream, 
 
 int vlasov_submit(vlasov_server *s, const vlasov_request *r, const double *f0_host, uint64_t *ticket)
 {
-    if (!s || !r || !f0_host || !ticket) return fail(VLASOV_E_INVAL, "NULL argument");
+    if (!s || !r || !ticket) return fail(VLASOV_E_INVAL, "NULL argument");
+    if (r->ic.kind == VLASOV_IC_HOST) {
+        if (!f0_host) return fail(VLASOV_E_INVAL, "f0_host is NULL for a request without a generated initial condition");
+    } else {
+        const std::string bad = validate_ic(&r->ic);
+        if (!bad.empty()) return fail(VLASOV_E_INVAL, bad);
+    }
     const std::string why = validate(&r->p);
     if (!why.empty()) return fail(VLASOV_E_INVAL, why);
     if (r->p.storage != s->storage) return fail(VLASOV_E_INVAL, "request storage differs from the server's");
@@ -559,7 +630,7 @@ int vlasov_submit(vlasov_server *s, const vlasov_request *r, const double *f0_ho
     if (bytes > s->arena_bytes - s->table_bytes) return fail(VLASOV_E_NOMEM, "request larger than the arena");
     vlasov_server::Pending p;
     p.req = *r;
-    p.f0.assign(f0_host, f0_host + (size_t)r->p.nx * (size_t)r->p.np);
+    if (r->ic.kind == VLASOV_IC_HOST) p.f0.assign(f0_host, f0_host + (size_t)r->p.nx * (size_t)r->p.np);
     p.t_submit = seconds_since(s->t0);
     {
         std::lock_guard<std::mutex> lk(s->mu);

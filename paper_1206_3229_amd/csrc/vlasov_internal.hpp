@@ -34,10 +34,9 @@ constexpr int DRIFT_NT = 128, DRIFT_V = 2, DRIFT_PF = 4;
 // kick rows per thread (measured best on 4096^2: 16 for FP64, 32 for FP32)
 template <typename T> constexpr int kick_rows() { return sizeof(T) == 8 ? 16 : 32; }
 // fused kick and drift: default tile width and blocks; rows requested ahead
-// by the kick (FP64: 2, which keeps the kernel within 96 VGPRs, five waves
-// per SIMD)
+// by the kick (FP64 within 96 VGPRs, five waves per SIMD)
 constexpr int KD_TW = 256, KD_RB = 1;
-template <typename T> constexpr int kd_pf() { return sizeof(T) == 8 ? 2 : 4; }
+template <typename T> constexpr int kd_pf() { return 4; }
 // rows per thread of the filter along p
 constexpr int FILTER_R = 16;
 // substeps of a step at most (the splittings of vlasov_splitting)
@@ -63,6 +62,9 @@ Layout layout_of(const vlasov_params &p);
 // "" if the parameters are valid, else the reason.
 std::string validate(const vlasov_params *p);
 
+// "" if the spec of a generated initial condition is valid, else the reason.
+std::string validate_ic(const vlasov_ic *ic);
+
 }  // namespace vlasov_detail
 
 struct vlasov_ctx {
@@ -77,6 +79,13 @@ struct vlasov_ctx {
     int64_t nblk;
     bool have_force;
     vlasov_tuning tune;  // launch shapes of the drift and kick
+    // HIP graphs of gsteps whole steps (vlasov_set_graph; 0: none), captured on
+    // cap_stream the first time they are needed, one per current buffer at the
+    // start
+    int gsteps = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int gcur_end[2] = {0, 0};  // current buffer after a replay
     // host copies kept alive for asynchronous uploads
     std::vector<int32_t> h_dm;
     std::vector<double4> h_dw;

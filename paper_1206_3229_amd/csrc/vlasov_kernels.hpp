@@ -553,290 +553,276 @@ static __global__ __launch_bounds__(256) void k_kick_filter(const T *__restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Step 3 fused with the drift that follows it (step 4, and with NPASS = 2 also
-// step 1 of the next step).  Once the force is known nothing global separates
-// the kick of a row from its drift, so one workgroup kicks the columns its
-// drift windows need and drifts the kicked rows straight from LDS: f is read
-// and written once for both sweeps.  The arithmetic of every value is that of
-// the separate kick and drift, so results are identical bit for bit.
+// Step 3 fused with the two half drifts that follow it (step 4 and step 1 of
+// the next step).  Once the force is known nothing global separates the kick
+// of a row from its drifts, so one workgroup kicks the columns its drift
+// windows need and drifts the kicked rows straight from LDS: f is read and
+// written once for the three sweeps.  The arithmetic of every value is that
+// of the separate kick and drifts, so results are identical bit for bit.
 //
-// Tile: RB consecutive density blocks (16 RB rows) by TW output columns, NT
-// threads.  The drift window of row j starts at column i0 + o_j - 4 NPASS,
-// o_j the sum of the row's drift offsets (m1_j + m2_j, or m1_j for NPASS =
-// 1); over the tile these windows lie in the KW = WIN + SPR kicked columns
-// starting at i0 + kbase (kbase = min_j o_j - 4 NPASS, reduced mod nx on a
-// periodic x axis), row j's window at offset krel_j = o_j - min o.  A grid
-// whose tiles need krel > SPR takes the separate kernels.  Thread t kicks the columns kappa = t + k NT (k < KC) of that
-// range, each from a sliding register window of its column (the kick of row
-// r needs the samples r - 4 + m .. r + 5 + m), requested PF rows ahead and
-// carried across the blocks of the tile, and writes the kicked row into the
-// LDS window of the drift at kappa - krel_j.  The taller the tile, the
-// smaller the share of the 10 halo rows the kick reads above and below it.
-// The rows are software-pipelined with one barrier per row: the kick of row
-// r, the first half drift of row r - 1 and the second of row r - 2 run
-// between two barriers, on two window and two intermediate row buffers.
+// Tile: RB consecutive density blocks (16 RB rows) by TW output columns.  The
+// first-pass window of row j starts at column i0 + o_j - 8, o_j = m1_j + m2_j
+// the sum of the row's two drift offsets; over the tile these windows lie in
+// the KW = TW + 18 + SPR kicked columns starting at i0 + kbase (kbase = min_j
+// o_j - 8, reduced mod nx on a periodic x axis), row j's window at offset
+// krel_j = o_j - min o.  A grid whose tiles need krel > SPR takes the
+// separate kernels.
+//
+// Work per row (one barrier per row, three rows in flight):
+//   kick of row r: every lane kicks one column (NT >= KW lanes) from a
+//     sliding register window of its column (the kick of row r needs the
+//     samples r - 4 + m .. r + 5 + m), loads requested PF rows ahead, and
+//     writes the kicked value to slot t of the row's LDS buffer;
+//   first half drift of row r - 1 (the first W1 waves): runs of V1 = 5
+//     adjacent intermediate values per lane, TW + 9 of them per row;
+//   second half drift of row r - 2 (the next W2 waves): runs of V2 = 4
+//     outputs per lane, stored to HBM, and their serial column sums over the
+//     block (density partial sums).
+// A run of V outputs shares its V + 1 stencils (V + 9 samples), so a lane
+// computes 1 + 1/V stencils per output instead of 2.
 // ---------------------------------------------------------------------------
 constexpr int KD_SPR = 8;
 
-template <int NPASS, int NT, int TW, int VR = 2>
-struct KickDriftGeom {
-    static constexpr int V = VR;  // adjacent outputs per thread in the half drifts
-    using G = DriftGeom<NPASS, NT, V, V * NT - TW>;
-    static constexpr int KW = G::WIN + KD_SPR;      // kicked columns per row
-    static constexpr int KC = (KW + NT - 1) / NT;  // kicked columns per thread
-    static_assert(NPASS == 1 || G::NRUN1 <= NT, "one first-pass run per thread");
-    static_assert(TW <= V * NT, "one output run per thread");
+template <int TW>
+struct KDGeom {
+    static constexpr int V1 = 5, V2 = 4;                  // outputs per lane in the two half drifts
+    static constexpr int MIDN = TW + 9;                   // first-pass values per row
+    static constexpr int NRUN1 = (MIDN + V1 - 1) / V1;    // first-pass lanes
+    static constexpr int NRUN2 = (TW + V2 - 1) / V2;      // second-pass lanes
+    static constexpr int W1 = (NRUN1 + 63) / 64, W2 = (NRUN2 + 63) / 64;
+    static constexpr int KW = TW + 18 + KD_SPR;           // kicked columns per row
+    static constexpr int NT = (KW + 63) / 64 * 64;        // one kicked column per lane
+    static constexpr int KLD = NT;                        // kicked-row buffer (slot = lane)
+    static constexpr int MLD = (NRUN1 * V1 + 3) / 4 * 4;  // first-pass row buffer
+    static_assert(W1 + W2 <= NT / 64, "both half drifts have waves of their own");
+    static_assert(KD_SPR + (NRUN1 - 1) * V1 + V1 + 9 <= KLD, "first-pass reads stay in the kicked row");
+    static_assert((NRUN2 - 1) * V2 + V2 + 9 <= MIDN, "second-pass reads stay in the first-pass row");
+    static_assert(TW % V2 == 0, "whole second-pass runs");
 };
 
-template <typename T, int NPASS, int BCX, int BCP, bool PARTIALS, int NT, int TW, int PF, int RB, int VR, int UB,
-          bool FULL>
+// V outputs of a run from V + 9 samples x (x[4 + k] the start of output k's
+// cell): V + 1 stencils shared by the run.
+template <typename T, int V>
+__device__ __forceinline__ void spline_run_regs(const T (&x)[V + 9], T a, T b, T g, T d, T (&o)[V])
+{
+    T D[V + 1];
+#pragma unroll
+    for (int k = 0; k <= V; ++k) D[k] = second_diff(x + 4 + k);
+#pragma unroll
+    for (int k = 0; k < V; ++k) o[k] = spline(a, b, g, d, x[4 + k], x[5 + k], D[k], D[k + 1]);
+}
+
+template <typename T, int BCX, int BCP, int TW, int PF, int RB, bool FULL>
 __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__restrict__ fout,
                                                 const double *__restrict__ F, double dt, double dp,
-                                                const int32_t *__restrict__ dm1, const double4 *__restrict__ dw1,
-                                                const int32_t *__restrict__ dm2, const double4 *__restrict__ dw2,
-                                                const int32_t *__restrict__ kbase, const int32_t *__restrict__ krel,
-                                                double *__restrict__ part, int nx, int np, int tx, int ty, T *win0,
-                                                T *win1, T *mid, typename Vec4<T>::type *kwt)
+                                                const int32_t *__restrict__ dm2, const double4 *__restrict__ dw1,
+                                                const double4 *__restrict__ dw2, const int32_t *__restrict__ kbase,
+                                                const int32_t *__restrict__ krel, double *__restrict__ part, int nx,
+                                                int np, int tx, int ty, T *kbuf, T *mbuf)
 {
-    using KG = KickDriftGeom<NPASS, NT, TW, VR>;
-    using G = typename KG::G;
-    constexpr int V = KG::V, KC = KG::KC, R = ROWS_PER_BLOCK;
+    using G = KDGeom<TW>;
+    constexpr int V1 = G::V1, V2 = G::V2, R = ROWS_PER_BLOCK, KLD = G::KLD, MLD = G::MLD;
     constexpr int NS = R + 10 + PF;  // window slots: samples of a block plus those requested ahead
-    constexpr int WIN = G::WIN, MIDN = G::MIDN, NRUN1 = G::NRUN1, LDW = G::LDW, LDM = G::LDM;
     static_assert(NS <= 32, "one mask bit per sample");
     const int t = threadIdx.x;
+    const int wave = t >> 6;
     const int i0 = tx * TW;
     const int j0 = ty * (R * RB);
     const int nr = FULL ? R * RB : min(R * RB, np - j0);  // rows of the tile
 
-    for (int s = WIN + t; s < LDW; s += NT) {
-        win0[s] = T(0);
-        win1[s] = T(0);
-    }
-    if (NPASS == 2)
-        for (int s = MIDN + t; s < LDM; s += NT) {
-            mid[s] = T(0);
-            mid[LDM + s] = T(0);
-        }
-
-    // Kicked columns of this thread: foot of the p shift (eq. step3), first
-    // sample row, and masks of the samples that lie inside the grid.
+    // The kicked column of this lane: foot of its p shift (eq. step3), the
+    // spline weights, and the element index of its first sample.
     const int cL = i0 + kbase[ty];
-    const T *colp[KC];
-    int rbase[KC];  // row of sample 0 of the current block (wrapped or unclamped)
-    uint32_t inside[KC];
-    bool colin[KC];
-    // FP64: the spline weights of the kicked columns live in LDS (slot t +
-    // k NT, read back by the same thread each row), which keeps the kernel
-    // within 96 VGPRs; FP32 keeps them in registers
-    constexpr bool KWL = sizeof(T) == 8;
-    T ka[KC], kb[KC], kg[KC], kd[KC];
-#pragma unroll
-    for (int k = 0; k < KC; ++k) {
-        const int c = cL + t + k * NT;
-        int gc;
-        if (BCX == BC_PERIODIC) {
-            gc = c >= nx ? c - nx : c;
-            gc = gc >= nx ? wrap(gc, nx) : gc;
-            colin[k] = true;
-        } else {
-            gc = min(max(c, 0), nx - 1);
-            colin[k] = c >= 0 && c < nx;
-        }
-        const Foot ft = foot_of_shift((F[gc] * dt) / dp);
-        const int m = reduce_offset(ft.m, np, BCP);
-        if constexpr (KWL) {
-            typename Vec4<T>::type kw;
-            kw.x = (T)ft.a;
-            kw.y = (T)ft.b;
-            kw.z = (T)ft.g;
-            kw.w = (T)ft.d;
-            kwt[t + k * NT] = kw;
-        } else {
-            ka[k] = (T)ft.a;
-            kb[k] = (T)ft.b;
-            kg[k] = (T)ft.g;
-            kd[k] = (T)ft.d;
-        }
-        colp[k] = fin + gc;
-        int b = j0 + m - 4;
-        if (BCP == BC_PERIODIC) b = wrap(b, np);
-        rbase[k] = b;
-        inside[k] = 0;
+    const int c = cL + t;
+    int gc;
+    bool colin = true;
+    if (BCX == BC_PERIODIC) {
+        gc = wrap(c, nx);
+    } else {
+        gc = min(max(c, 0), nx - 1);
+        colin = c >= 0 && c < nx;
     }
-    // Sample s of column k in the current block: row rbase + s, wrapped or
-    // clamped (zero rows are masked when the sample is first used, never next
-    // to its load).  rbase < np and s < NS <= 32 <= 2 np, so two wraps suffice.
-    T w[KC][NS];
+    // every kicked column lies inside the grid (or the axis is periodic): no mask
+    const bool kick_in = BCX == BC_PERIODIC || (cL >= 0 && cL + G::KW <= nx);
+    const Foot ft = foot_of_shift((F[gc] * dt) / dp);
+    const int m = reduce_offset(ft.m, np, BCP);
+    const T ka = (T)ft.a, kb = (T)ft.b, kg = (T)ft.g, kd = (T)ft.d;
+    const uint32_t total = (uint32_t)np * (uint32_t)nx;
+    // periodic p: element index of the next sample to request (one row per
+    // request, wrapped by one subtraction); zero p: row of sample 0
+    int rb0 = j0 + m - 4;
+    uint32_t nidx = 0;
+    if (BCP == BC_PERIODIC) {
+        rb0 = wrap(rb0, np);
+        nidx = (uint32_t)rb0 * (uint32_t)nx + (uint32_t)gc;
+    }
+    uint32_t inside = 0;  // zero p: bit s says that sample s lies in the grid
+    T w[NS];
     auto request = [&](int s) {
-#pragma unroll
-        for (int k = 0; k < KC; ++k) {
-            int q = rbase[k] + s;
-            if (BCP == BC_PERIODIC) {
-                q = q >= np ? q - np : q;
-                q = q >= np ? q - np : q;
-            } else {
-                inside[k] |= (uint32_t)(q >= 0 && q < np) << s;
-                q = min(max(q, 0), np - 1);
-            }
-            w[k][s] = colp[k][(size_t)q * nx];
+        // sample s of the window (of the current block)
+        if (BCP == BC_PERIODIC) {
+            w[s] = fin[nidx];
+            nidx += (uint32_t)nx;
+            nidx = min(nidx, nidx - total);  // unsigned: subtracts total once past the end
+        } else {
+            const int q = rb0 + s;
+            inside |= (uint32_t)(q >= 0 && q < np) << s;
+            w[s] = fin[(size_t)min(max(q, 0), np - 1) * (size_t)nx + (size_t)gc];
         }
     };
     auto settle = [&](int s) {
-        if (BCP != BC_PERIODIC) {
-#pragma unroll
-            for (int k = 0; k < KC; ++k) w[k][s] = (inside[k] >> s & 1u) ? w[k][s] : T(0);
-        }
+        if (BCP != BC_PERIODIC) w[s] = (inside >> s & 1u) ? w[s] : T(0);
     };
 #pragma unroll
     for (int s = 0; s < 10 + PF; ++s) request(s);
 #pragma unroll
     for (int s = 0; s < 9; ++s) settle(s);
-    T Dk[KC];
-#pragma unroll
-    for (int k = 0; k < KC; ++k) Dk[k] = second_diff(w[k] + 4);
+    T Dk = second_diff(w + 4);
 
-    const int i = i0 + V * t;
-    const bool own = FULL ? V * t < TW : (V * t < TW && i < nx);
-    // UB = RB unrolls the blocks (the window slide becomes register renaming)
-#pragma unroll UB
+    const bool pass1 = wave < G::W1;
+    const bool pass2 = wave >= G::W1 && wave < G::W1 + G::W2;
+    const int u1 = t, u2 = t - 64 * G::W1;  // run of the lane in its pass
+    const int i = i0 + V2 * u2;             // first output column of a second-pass lane
+    const bool own2 = pass2 && u2 < G::NRUN2 && (FULL || i < nx);
+    const bool own1 = pass1 && u1 < G::NRUN1;
+
     for (int blk = 0; blk < RB; ++blk) {
         const int jb = j0 + R * blk;
         if (!FULL && R * blk >= nr) break;  // uniform
-        double acc[V];
+        double acc[V2];
 #pragma unroll
-        for (int k = 0; k < V; ++k) acc[k] = 0.0;
-        // Three stages in flight, one barrier per row: the kick of row r, the
-        // first half drift of row r - 1 and the second of row r - 2 (for
-        // NPASS = 1: the kick of row r and the half drift of row r - 1).
-        // Rows alternate between two window and two intermediate buffers.
-        constexpr int LAG = NPASS == 2 ? 2 : 1;
+        for (int k = 0; k < V2; ++k) acc[k] = 0.0;
 #pragma unroll
-        for (int r = 0; r < R + LAG; ++r) {
+        for (int r = 0; r < R + 2; ++r) {
             if (r < R && (FULL || R * blk + r < nr)) {
-                const int j = jb + r;
-                T *wrow = (r & 1) ? win1 : win0;
+                // kick of row r into slot t of its buffer
                 settle(r + 9);
-                const int rel = krel[j];
-#pragma unroll
-                for (int k = 0; k < KC; ++k) {
-                    const T Dk1 = second_diff(w[k] + r + 5);
-                    T y;
-                    if constexpr (KWL) {
-                        const typename Vec4<T>::type kw = kwt[t + k * NT];
-                        y = spline(kw.x, kw.y, kw.z, kw.w, w[k][r + 4], w[k][r + 5], Dk[k], Dk1);
-                    } else {
-                        y = spline(ka[k], kb[k], kg[k], kd[k], w[k][r + 4], w[k][r + 5], Dk[k], Dk1);
-                    }
-                    Dk[k] = Dk1;
-                    if (BCX != BC_PERIODIC) y = colin[k] ? y : T(0);
-                    const int pos = t + k * NT - rel;
-                    wrow[(unsigned)pos < (unsigned)WIN ? pos : LDW] = y;
-                }
-                // the samples of the next block are requested too (clamped
-                // or wrapped addresses; unused after the last block)
+                const T Dk1 = second_diff(w + r + 5);
+                T y = spline(ka, kb, kg, kd, w[r + 4], w[r + 5], Dk, Dk1);
+                Dk = Dk1;
+                if (!kick_in) y = colin ? y : T(0);
+                kbuf[(r & 1) * KLD + t] = y;
+                // samples of the next block are requested too (the last
+                // block's extra requests read valid rows and are unused)
                 if (r + 10 + PF < NS && (RB > 1 || r + 10 + PF < R + 10)) request(r + 10 + PF);
             }
-            if (NPASS == 2 && r >= 1 && r - 1 < R && (FULL || R * blk + r - 1 < nr)) {
-                // first half drift (table 1) at positions i0 + m - 4 + q,
-                // q in [0, TW + 9), m the offset of the second
+            if (r >= 1 && r - 1 < R && (FULL || R * blk + r - 1 < nr) && own1) {
+                // first half drift (table 1) of row r - 1 at the positions
+                // i0 + m2 - 4 + q, q in [0, TW + 9), that the second reads
                 const int q1 = r - 1, j = jb + q1;
-                const T *src = (q1 & 1) ? win1 : win0;
-                T *mrow = mid + ((q1 & 1) ? LDM : 0);
+                const T *src = kbuf + (q1 & 1) * KLD + krel[j] + V1 * u1;
                 const double4 w1 = dw1[j];
-                const int m = dm2[j];
-                if (t < NRUN1) {
-                    T o[V];
-                    spline_run<T, V>(src, t, (T)w1.x, (T)w1.y, (T)w1.z, (T)w1.w, o);
-                    if (BCX == BC_ZERO) {
-                        const int q = i0 + m - 4 + V * t;
+                T x[V1 + 9], o[V1];
 #pragma unroll
-                        for (int k = 0; k < V; ++k)
+                for (int k = 0; k < V1 + 9; ++k) x[k] = src[k];
+                spline_run_regs<T, V1>(x, (T)w1.x, (T)w1.y, (T)w1.z, (T)w1.w, o);
+                if (BCX == BC_ZERO) {
+                    const int lo = i0 + dm2[j] - 4;  // position of first-pass value 0
+                    if (!(lo >= 0 && lo + G::MIDN <= nx)) {
+                        const int q = lo + V1 * u1;
+#pragma unroll
+                        for (int k = 0; k < V1; ++k)
                             if (q + k < 0 || q + k >= nx) o[k] = T(0);
                     }
-#pragma unroll
-                    for (int k = 0; k < V; k += 2) {
-                        typename Vec2<T>::type ww;
-                        ww.x = o[k];
-                        ww.y = o[k + 1];
-                        reinterpret_cast<typename Vec2<T>::type *>(mrow + V * t)[k / 2] = ww;
-                    }
                 }
+                T *dst = mbuf + (q1 & 1) * MLD + V1 * u1;
+#pragma unroll
+                for (int k = 0; k < V1; ++k) dst[k] = o[k];
             }
-            if (r >= LAG && (FULL || R * blk + r - LAG < nr)) {
-                const int q2 = r - LAG, j = jb + q2;
-                const T *src = NPASS == 2 ? mid + ((q2 & 1) ? LDM : 0) : ((q2 & 1) ? win1 : win0);
-                const double4 wd = (NPASS == 2 ? dw2 : dw1)[j];
-                if (own) {
-                    T o[V];
-                    spline_run<T, V>(src, t, (T)wd.x, (T)wd.y, (T)wd.z, (T)wd.w, o);
-                    if (FULL) {
+            if (r >= 2 && (FULL || R * blk + r - 2 < nr) && own2) {
+                // second half drift (table 2) of row r - 2: outputs i .. i + 3
+                const int q2 = r - 2, j = jb + q2;
+                const T *src = mbuf + (q2 & 1) * MLD + V2 * u2;
+                const double4 wd = dw2[j];
+                T x[V2 + 9], o[V2];
+                using V4 = typename Vec4<T>::type;
+                using VV2 = typename Vec2<T>::type;
+                if constexpr (sizeof(T) == 8) {
 #pragma unroll
-                        for (int k = 0; k < V; k += 2) {
-                            typename Vec2<T>::type ww;
-                            ww.x = o[k];
-                            ww.y = o[k + 1];
-                            *reinterpret_cast<typename Vec2<T>::type *>(fout + (size_t)j * nx + i + k) = ww;
-                        }
-                    } else {
-                        store_run<T, V>(fout + (size_t)j * nx, i, nx, o);
+                    for (int k = 0; k < 6; ++k) {
+                        const VV2 v = reinterpret_cast<const VV2 *>(src)[k];
+                        x[2 * k] = v.x;
+                        x[2 * k + 1] = v.y;
                     }
-                    if (PARTIALS) {
+                    x[12] = src[12];
+                } else {
 #pragma unroll
-                        for (int k = 0; k < V; ++k) acc[k] = acc[k] + (double)o[k];
+                    for (int k = 0; k < 3; ++k) {
+                        const V4 v = reinterpret_cast<const V4 *>(src)[k];
+                        x[4 * k] = v.x;
+                        x[4 * k + 1] = v.y;
+                        x[4 * k + 2] = v.z;
+                        x[4 * k + 3] = v.w;
                     }
+                    x[12] = src[12];
                 }
+                spline_run_regs<T, V2>(x, (T)wd.x, (T)wd.y, (T)wd.z, (T)wd.w, o);
+                T *row = fout + (size_t)j * nx;
+                if (FULL) {
+                    if constexpr (sizeof(T) == 8) {
+                        VV2 *p = reinterpret_cast<VV2 *>(row + i);
+                        VV2 a, b;
+                        a.x = o[0];
+                        a.y = o[1];
+                        b.x = o[2];
+                        b.y = o[3];
+                        p[0] = a;
+                        p[1] = b;
+                    } else {
+                        V4 a;
+                        a.x = o[0];
+                        a.y = o[1];
+                        a.z = o[2];
+                        a.w = o[3];
+                        *reinterpret_cast<V4 *>(row + i) = a;
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < V2; ++k)
+                        if (i + k < nx) row[i + k] = o[k];
+                }
+#pragma unroll
+                for (int k = 0; k < V2; ++k) acc[k] = acc[k] + (double)o[k];
             }
             __syncthreads();
         }
-        if (PARTIALS && own) {
+        if (own2) {
             double *prow = part + (size_t)(ty * RB + blk) * nx;
 #pragma unroll
-            for (int k = 0; k < V; ++k)
+            for (int k = 0; k < V2; ++k)
                 if (FULL || i + k < nx) prow[i + k] = acc[k];
         }
-        // slide the windows by one block: sample s + 16 becomes sample s
+        // slide the window by one block: sample s + 16 becomes sample s
         if (RB > 1) {
 #pragma unroll
-            for (int k = 0; k < KC; ++k) {
-#pragma unroll
-                for (int s = 0; s + R < NS; ++s) w[k][s] = w[k][s + R];
-                inside[k] >>= R;
-                rbase[k] += R;
-                if (BCP == BC_PERIODIC) rbase[k] = rbase[k] >= np ? rbase[k] - np : rbase[k];
-            }
+            for (int s = 0; s + R < NS; ++s) w[s] = w[s + R];
+            inside >>= R;
+            rb0 += R;
         }
     }
 }
 
-// Waves per SIMD: FP64 five (within 96 VGPRs with the kick weights in LDS
-// and two rows of prefetch); FP32 six (at most 80 VGPRs), measured faster
-// than the compiler's own five despite a few spilled registers.
-template <typename T, int NPASS, int BCX, int BCP, bool PARTIALS, int NT, int TW, int PF, int RB, int VR = 2,
-          int UB = 1>
-static __global__ __launch_bounds__(NT, sizeof(T) == 8 ? 5 : 6) void k_kick_drift(const T *__restrict__ fin, T *__restrict__ fout,
-                                                   const double *__restrict__ F, double dt, double dp,
-                                                   const int32_t *__restrict__ dm1,
-                                                   const double4 *__restrict__ dw1,
-                                                   const int32_t *__restrict__ dm2,
-                                                   const double4 *__restrict__ dw2,
-                                                   const int32_t *__restrict__ kbase,
-                                                   const int32_t *__restrict__ krel, double *__restrict__ part,
-                                                   int nx, int np, int ntx, int nty)
+// FP64: at most 96 VGPRs (five waves per SIMD); FP32 at most 80 (six).
+template <typename T, int BCX, int BCP, int TW, int PF, int RB>
+static __global__ __launch_bounds__(KDGeom<TW>::NT) void k_kick_drift(
+    const T *__restrict__ fin, T *__restrict__ fout, const double *__restrict__ F, double dt, double dp,
+    const int32_t *__restrict__ dm2, const double4 *__restrict__ dw1, const double4 *__restrict__ dw2,
+    const int32_t *__restrict__ kbase, const int32_t *__restrict__ krel, double *__restrict__ part, int nx, int np,
+    int ntx, int nty)
 {
-    using G = typename KickDriftGeom<NPASS, NT, TW, VR>::G;
-    __shared__ __attribute__((aligned(16))) T win[2][G::LDA];
-    __shared__ __attribute__((aligned(16))) T mid[2 * G::LDM];  // two intermediate rows
-    __shared__ typename Vec4<T>::type kwt[sizeof(T) == 8 ? KickDriftGeom<NPASS, NT, TW, VR>::KC * NT : 1];
+    using G = KDGeom<TW>;
+    __shared__ __attribute__((aligned(16))) T kbuf[2 * G::KLD];  // two kicked rows
+    __shared__ __attribute__((aligned(16))) T mbuf[2 * G::MLD];  // two first-pass rows
     int tx, ty;
     if (!xcd_tile(ntx, nty, tx, ty)) return;
-    const bool full = (ty + 1) * (ROWS_PER_BLOCK * RB) <= np && (tx + 1) * TW <= nx && (nx & 1) == 0;
+    constexpr int VA = sizeof(T) == 8 ? 2 : 4;  // vector stores need rows aligned to VA values
+    const bool full = (ty + 1) * (ROWS_PER_BLOCK * RB) <= np && (tx + 1) * TW <= nx && nx % VA == 0;
     if (full)
-        kick_drift_tile<T, NPASS, BCX, BCP, PARTIALS, NT, TW, PF, RB, VR, UB, true>(
-            fin, fout, F, dt, dp, dm1, dw1, dm2, dw2, kbase, krel, part, nx, np, tx, ty, win[0], win[1], mid, kwt);
+        kick_drift_tile<T, BCX, BCP, TW, PF, RB, true>(fin, fout, F, dt, dp, dm2, dw1, dw2, kbase, krel, part, nx,
+                                                       np, tx, ty, kbuf, mbuf);
     else
-        kick_drift_tile<T, NPASS, BCX, BCP, PARTIALS, NT, TW, PF, RB, VR, UB, false>(
-            fin, fout, F, dt, dp, dm1, dw1, dm2, dw2, kbase, krel, part, nx, np, tx, ty, win[0], win[1], mid, kwt);
+        kick_drift_tile<T, BCX, BCP, TW, PF, RB, false>(fin, fout, F, dt, dp, dm2, dw1, dw2, kbase, krel, part, nx,
+                                                        np, tx, ty, kbuf, mbuf);
 }
 
 // ---------------------------------------------------------------------------
@@ -1127,7 +1113,23 @@ __device__ inline void magnetization(const double *rho, const double *cs, const 
 {
     const int lane = threadIdx.x & 63;
     double c = 0.0, s = 0.0;
-    for (int i = lane; i < n; i += 64) {
+    int i = lane;
+    // eight terms of each chain requested at once (the chains stay in order)
+    for (; i + 7 * 64 < n; i += 8 * 64) {
+        double cv[8], sv[8], rv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            cv[u] = cs[i + 64 * u];
+            sv[u] = sn[i + 64 * u];
+            rv[u] = rho[i + 64 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            c = fma(cv[u], rv[u], c);
+            s = fma(sv[u], rv[u], s);
+        }
+    }
+    for (; i < n; i += 64) {
         c = fma(cs[i], rho[i], c);
         s = fma(sn[i], rho[i], s);
     }
@@ -1233,7 +1235,21 @@ __device__ __forceinline__ void force_ring_output(const double *__restrict__ rho
 {
     const int lane = threadIdx.x & 63;
     double acc = 0.0;
-    for (int k = lane; k < n; k += 64) {
+    int k = lane;
+    // eight terms of the chain requested at once (the chain stays in order)
+    for (; k + 7 * 64 < n; k += 8 * 64) {
+        double kv[8], rv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            int d = i - (k + 64 * u);
+            if (d < 0) d += n;
+            kv[u] = K[d];
+            rv[u] = rho[k + 64 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fma(kv[u], rv[u], acc);
+    }
+    for (; k < n; k += 64) {
         int d = i - k;
         if (d < 0) d += n;
         acc = fma(K[d], rho[k], acc);
@@ -1285,7 +1301,16 @@ __device__ __forceinline__ void force_sheet_block(const double *__restrict__ rho
         const int l = threadIdx.x;
         const int len = min(c, n - l * c);  // <= 0 past the end
         double tot = 0.0;
-        for (int k = 0; k < len; ++k) tot = tot + (STAGED ? L[k * 65 + l] : rho[l * c + k]);
+        int k = 0;
+        // sixteen samples requested at once, summed in order
+        for (; k + 16 <= len; k += 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = STAGED ? L[(k + u) * 65 + l] : rho[l * c + k + u];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) tot = tot + v[u];
+        }
+        for (; k < len; ++k) tot = tot + (STAGED ? L[k * 65 + l] : rho[l * c + k]);
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const double v = __shfl_up(tot, d, 64);
@@ -1295,16 +1320,24 @@ __device__ __forceinline__ void force_sheet_block(const double *__restrict__ rho
         if (l == 0) excl = 0.0;
         const double S = __shfl(tot, 63, 64);
         double acc = 0.0;
-        for (int k = 0; k < len; ++k) {
-            const double r = STAGED ? L[k * 65 + l] : rho[l * c + k];
+        auto one = [&](int kk, double r) {
             const double Pi = excl + acc;
             const double f = K * (fma(-2.0, Pi, S) - r);
             if (STAGED)
-                L[k * 65 + l] = f;
+                L[kk * 65 + l] = f;
             else
-                F[l * c + k] = f;
+                F[l * c + kk] = f;
             acc = acc + r;
+        };
+        k = 0;
+        for (; k + 16 <= len; k += 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = STAGED ? L[(k + u) * 65 + l] : rho[l * c + k + u];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) one(k + u, v[u]);
         }
+        for (; k < len; ++k) one(k, STAGED ? L[k * 65 + l] : rho[l * c + k]);
     }
     if (STAGED) {
         __syncthreads();
@@ -1498,6 +1531,7 @@ struct GridDesc {
     int64_t hcap;
     int32_t nx, np, nblk, model, bc_x, bc_p;
     double dx, dp, dt, sheetK;
+    const int32_t *kbase, *krel;  // fused kick and drift: tables of 256-column, 16-row tiles
 };
 
 struct Cycle {
@@ -1506,8 +1540,12 @@ struct Cycle {
     int8_t drift[BATCH_MAX];     // DRIFT_* (FIRST and PAIR also write density partial sums)
     int8_t kick[BATCH_MAX];      // density, force and kick in this cycle
     int8_t cur[BATCH_MAX];       // current f buffer at the start of the cycle
+    int8_t kin[BATCH_MAX];       // f buffer the kick (or fused kick and drift) reads
     int8_t pad[4];
-    int32_t off_drift[BATCH_MAX + 1], off_dens[BATCH_MAX + 1], off_force[BATCH_MAX + 1], off_kick[BATCH_MAX + 1];
+    // work items of the phases: drift tiles, density blocks, force items,
+    // tiles of the separate kick, tiles of the fused kick and two half drifts
+    int32_t off_drift[BATCH_MAX + 1], off_dens[BATCH_MAX + 1], off_force[BATCH_MAX + 1], off_kick[BATCH_MAX + 1],
+        off_kd[BATCH_MAX + 1];
 };
 
 // Member owning work item e: the last a with off[a] <= e (off[0] = 0 <= e < off[n]).
@@ -1629,13 +1667,55 @@ static __global__ __launch_bounds__(256) void kb_kick(const GridDesc *__restrict
         const int li = e - cy->off_kick[a];
         const int ntx = (g.nx + 255) / 256;
         const int tx = li % ntx, ty = li / ntx;
-        const int cur = cy->cur[a];  // the drift of this cycle left f in buffer cur ^ 1
-        const T *fin = (const T *)g.f[cur ^ 1];
-        T *fout = (T *)g.f[cur];
+        const int kin = cy->kin[a];
+        const T *fin = (const T *)g.f[kin];
+        T *fout = (T *)g.f[kin ^ 1];
         if (g.bc_p == BC_PERIODIC)
             kick_tile<T, BC_PERIODIC, R>(fin, fout, g.Fkick, g.dt, g.dp, g.nx, g.np, tx, ty);
         else
             kick_tile<T, BC_ZERO, R>(fin, fout, g.Fkick, g.dt, g.dp, g.nx, g.np, tx, ty);
+    }
+}
+
+// The kick fused with the two half drifts after it (the second of one step,
+// the first of the next) for the members whose tables allow it: tiles of 256
+// columns by 16 rows, as the single-grid kernel.  Periodic p only.
+template <typename T, int PF>
+static __global__ __launch_bounds__(KDGeom<256>::NT) void kb_kick_drift(const GridDesc *__restrict__ gd,
+                                                                        const Cycle *__restrict__ cy)
+{
+    using G = KDGeom<256>;
+    __shared__ __attribute__((aligned(16))) T kbuf[2 * G::KLD];
+    __shared__ __attribute__((aligned(16))) T mbuf[2 * G::MLD];
+    constexpr int VA = sizeof(T) == 8 ? 2 : 4;
+    const int n = cy->n;
+    const int total = cy->off_kd[n];
+    for (int e = blockIdx.x; e < total; e += gridDim.x) {
+        const int a = find_member(cy->off_kd, n, e);
+        const GridDesc &g = gd[cy->slot[a]];
+        const int li = e - cy->off_kd[a];
+        const int ntx = (g.nx + 255) / 256;
+        const int tx = li % ntx, ty = li / ntx;
+        const int kin = cy->kin[a];
+        const T *fin = (const T *)g.f[kin];
+        T *fout = (T *)g.f[kin ^ 1];
+        const bool full = (ty + 1) * ROWS_PER_BLOCK <= g.np && (tx + 1) * 256 <= g.nx && g.nx % VA == 0;
+        __syncthreads();  // the previous item's LDS rows are consumed
+#define KDB(BX, FL)                                                                                                  \
+    kick_drift_tile<T, BX, BC_PERIODIC, 256, PF, 1, FL>(fin, fout, g.Fkick, g.dt, g.dp, g.dm, g.dw, g.dw, g.kbase,      \
+                                                        g.krel, g.part, g.nx, g.np, tx, ty, kbuf, mbuf)
+        if (g.bc_x == BC_PERIODIC) {
+            if (full)
+                KDB(BC_PERIODIC, true);
+            else
+                KDB(BC_PERIODIC, false);
+        } else {
+            if (full)
+                KDB(BC_ZERO, true);
+            else
+                KDB(BC_ZERO, false);
+        }
+#undef KDB
     }
 }
 

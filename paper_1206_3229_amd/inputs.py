@@ -122,8 +122,11 @@ def waterbag_halfwidths(M0: float, U: float) -> tuple[float, float]:
 
 
 def _normalise(raw: np.ndarray, dx: float, dp: float) -> np.ndarray:
-    # row sums by numpy, their total exactly rounded: deterministic for a given array
-    total = math.fsum(np.sum(raw, axis=1).tolist()) * dx * dp
+    """raw / ((S dx) dp), S the sum of raw in index order: each row serially
+    from i = 0 (cumsum accumulates in order), then the row sums from j = 0.
+    Any generator of the same raw values can reproduce S bit for bit."""
+    rows = np.cumsum(raw, axis=1)[:, -1]
+    total = float(np.cumsum(rows)[-1]) * dx * dp
     if not total > 0.0:
         raise ValueError("empty initial condition")
     return raw / total
@@ -157,7 +160,10 @@ def gaussian(p: Params, T: float, amp: float, seed: int = 0) -> np.ndarray:
     phi = 0.0 if seed == 0 else 2.0 * math.pi * float(uniform01(seed, np.zeros(1, np.uint64))[0])
     x = nodes(p.nx, p.xmin, p.xmax)
     v = nodes(p.np_, p.pmin, p.pmax)
-    raw = np.exp(-(v * v) / (2.0 * T))[:, None] * (1.0 + amp * np.cos(x - phi))[None, :]
+    # exp and cos of the C library, once per node
+    e = np.array([math.exp(-(vj * vj) / (2.0 * T)) for vj in v.tolist()])
+    c = np.array([1.0 + amp * math.cos(xi - phi) for xi in x.tolist()])
+    raw = e[:, None] * c[None, :]
     return _normalise(raw, p.dx, p.dp)
 
 

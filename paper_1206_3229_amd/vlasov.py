@@ -50,8 +50,30 @@ class Tuning(C.Structure):
                 ("kick_drift_blocks", C.c_int32)]
 
 
+IC_HOST, IC_WATERBAG, IC_WATERBAG_UM, IC_GAUSSIAN = 0, 1, 2, 3
+
+
+class IC(C.Structure):
+    """Initial condition generated on the device (vlasov_ic)."""
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("a0", C.c_double), ("a1", C.c_double),
+                ("amp", C.c_double), ("seed", C.c_uint64)]
+
+
+def ic_waterbag(x0: float, p0: float, amp: float = 0.0, seed: int = 0) -> IC:
+    return IC(IC_WATERBAG, 0, float(x0), float(p0), float(amp), int(seed))
+
+
+def ic_waterbag_um(U: float, M0: float, amp: float = 0.0, seed: int = 0) -> IC:
+    return IC(IC_WATERBAG_UM, 0, float(U), float(M0), float(amp), int(seed))
+
+
+def ic_gaussian(T: float, amp: float, seed: int = 0) -> IC:
+    return IC(IC_GAUSSIAN, 0, float(T), 0.0, float(amp), int(seed))
+
+
 class Request(C.Structure):
-    _fields_ = [("p", Params), ("nsteps", C.c_int64), ("keep_f", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("p", Params), ("nsteps", C.c_int64), ("keep_f", C.c_int32), ("reserved", C.c_int32),
+                ("ic", IC)]
 
 
 class Result(C.Structure):
@@ -84,6 +106,7 @@ def load() -> C.CDLL:
             "vlasov_init": (C.c_int, [P, _D, V, V, V, C.POINTER(V)]),
             "vlasov_set_external_force": (C.c_int, [V, _D]),
             "vlasov_step": (C.c_int, [V, C.c_int64]),
+            "vlasov_set_graph": (C.c_int, [V, C.c_int32]),
             "vlasov_drift": (C.c_int, [V, C.c_int32]),
             "vlasov_force": (C.c_int, [V, _D, _D]),
             "vlasov_kick": (C.c_int, [V]),
@@ -91,6 +114,7 @@ def load() -> C.CDLL:
             "vlasov_mag_history": (C.c_int, [V, _D, _D, C.c_int64, C.POINTER(C.c_int64)]),
             "vlasov_read_f": (C.c_int, [V, _D]),
             "vlasov_write_f": (C.c_int, [V, _D]),
+            "vlasov_generate_ic": (C.c_int, [V, C.POINTER(IC)]),
             "vlasov_destroy": (C.c_int, [V]),
             "vlasov_last_error": (C.c_char_p, []),
             "vlasov_profile_enable": (C.c_int, [V, C.c_int32]),
@@ -164,19 +188,33 @@ class Solver:
             self.f_buf = torch.empty(fb, dtype=torch.uint8, device=self.device)
             self.ws_buf = torch.empty(wb, dtype=torch.uint8, device=self.device)
             self.stream = torch.cuda.current_stream(self.device)
-        f0 = np.ascontiguousarray(f0, dtype=np.float64)
-        if f0.shape != (params.np_, params.nx):
-            raise ValueError(f"f0 shape {f0.shape} != (np, nx) = {(params.np_, params.nx)}")
+        # f0: the initial f as an FP64 [np][nx] array, or an IC generated on the device
+        gen = f0 if isinstance(f0, IC) else None
+        if gen is None:
+            f0 = np.ascontiguousarray(f0, dtype=np.float64)
+            if f0.shape != (params.np_, params.nx):
+                raise ValueError(f"f0 shape {f0.shape} != (np, nx) = {(params.np_, params.nx)}")
+        f0p = None if gen is not None else _dptr(f0)
         ctx = C.c_void_p()
-        check(lib.vlasov_init(C.byref(self._p), _dptr(f0), C.c_void_p(self.f_buf.data_ptr()),
+        check(lib.vlasov_init(C.byref(self._p), f0p, C.c_void_p(self.f_buf.data_ptr()),
                               C.c_void_p(self.ws_buf.data_ptr()), C.c_void_p(self.stream.cuda_stream),
                               C.byref(ctx)))
         self._ctx = ctx
         self.nx, self.np_ = params.nx, params.np_
+        if gen is not None:
+            self.generate_ic(gen)
+
+    def generate_ic(self, ic: "IC"):
+        """Replace f by an initial condition generated on the device."""
+        check(load().vlasov_generate_ic(self._ctx, C.byref(ic)))
 
     # -- steps -----------------------------------------------------------
     def step(self, nsteps: int = 1):
         check(load().vlasov_step(self._ctx, int(nsteps)))
+
+    def set_graph(self, steps_per_graph: int):
+        """Steps per HIP graph launch in step() (0: no graphs)."""
+        check(load().vlasov_set_graph(self._ctx, int(steps_per_graph)))
 
     def drift(self, npass: int = 1):
         check(load().vlasov_drift(self._ctx, int(npass)))
@@ -293,12 +331,18 @@ class Server:
         self._srv = srv
         self._shapes = {}
 
-    def submit(self, params, f0: np.ndarray, nsteps: int, keep_f: bool = False) -> int:
-        f0 = np.ascontiguousarray(f0, dtype=np.float64)
-        assert f0.shape == (params.np_, params.nx)
-        req = Request(to_params(params, 0), int(nsteps), 1 if keep_f else 0, 0)
+    def submit(self, params, f0, nsteps: int, keep_f: bool = False) -> int:
+        """f0: FP64 [np][nx] array, or an IC the server generates on the device."""
+        if isinstance(f0, IC):
+            req = Request(to_params(params, 0), int(nsteps), 1 if keep_f else 0, 0, f0)
+            f0p = None
+        else:
+            f0 = np.ascontiguousarray(f0, dtype=np.float64)
+            assert f0.shape == (params.np_, params.nx)
+            req = Request(to_params(params, 0), int(nsteps), 1 if keep_f else 0, 0, IC())
+            f0p = _dptr(f0)
         t = C.c_uint64()
-        check(load().vlasov_submit(self._srv, C.byref(req), _dptr(f0), C.byref(t)))
+        check(load().vlasov_submit(self._srv, C.byref(req), f0p, C.byref(t)))
         self._shapes[t.value] = (params.np_, params.nx, keep_f)
         return t.value
 
@@ -311,7 +355,8 @@ class Server:
         if rc == PENDING:
             return None
         self._shapes.pop(ticket, None)
-        return r.as_dict(), f
+        # a failed request returns no f
+        return r.as_dict(), (f if r.status == OK else None)
 
     def stats(self):
         q, r, d = C.c_int64(), C.c_int64(), C.c_int64()

@@ -77,7 +77,9 @@ def test_null_and_misaligned_pointers_rejected(lib):
     p = _params()
     ctx = C.c_void_p()
     f0 = (C.c_double * (64 * 32))()
-    assert lib.vlasov_init(C.byref(p), None, C.c_void_p(256), C.c_void_p(512), None, C.byref(ctx)) == -1
+    # f0_host may be NULL (f generated later); the device buffers may not
+    assert lib.vlasov_init(C.byref(p), f0, None, C.c_void_p(512), None, C.byref(ctx)) == -1
+    assert lib.vlasov_init(C.byref(p), f0, C.c_void_p(256), None, None, C.byref(ctx)) == -1
     assert lib.vlasov_init(C.byref(p), f0, C.c_void_p(260), C.c_void_p(512), None, C.byref(ctx)) == -1
     assert "aligned" in lib.vlasov_last_error().decode()
 

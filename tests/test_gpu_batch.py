@@ -220,3 +220,40 @@ def test_autotune_picks_a_compiled_shape(V, tmp_path, monkeypatch):
             best["kick_drift_blocks"]) in V.tuning_candidates()
     assert len(best["table"]) == len(V.tuning_candidates())
     assert autotune.tune(p, f0)["us_per_step"] == best["us_per_step"]  # served from the cache
+
+
+def test_server_chunk_failure_fails_the_running_requests(V, oracle, monkeypatch):
+    # a failure of the third chunk, injected on the host after its planning and
+    # before anything is enqueued: the three requests running then come back
+    # with the error and the steps finished before it, and the server goes on
+    # with a request submitted afterwards
+    th0, p0 = I.waterbag_halfwidths(0.5, 0.69)
+    p = I.Params(I.MODEL_HMF, 64, 64, -math.pi, math.pi, -2.5, 2.5, 0.1, storage=1)
+    monkeypatch.setenv("VLASOV_TEST_FAIL_CHUNK", "2")
+    srv = V.Server(64 << 20, storage=1, max_slots=8, chunk_cycles=4)
+    monkeypatch.delenv("VLASOV_TEST_FAIL_CHUNK")
+    f0s = [I.waterbag(p, th0, p0, 1e-4, k) for k in range(4)]
+
+    def wait(t):
+        t_end = time.time() + 60
+        while time.time() < t_end:
+            r = srv.poll(t)
+            if r is not None:
+                return r
+            time.sleep(0.002)
+        raise AssertionError("server did not finish")
+
+    # submitted together: all three are running when the third chunk fails
+    tickets = [srv.submit(p, f0s[k], 50, keep_f=True) for k in range(3)]
+    done = []
+    for t in tickets:
+        r, f = wait(t)
+        assert r["status"] == V.E_HIP and f is None
+        assert 0 <= r["steps_done"] < 50
+        done.append(r["steps_done"])
+    assert max(done) > 0  # the first admitted finished two chunks before the failure
+    later = srv.submit(p, f0s[3], 10, keep_f=True)
+    r, f = wait(later)
+    srv.close()
+    assert r["status"] == 0 and r["steps_done"] == 10
+    assert np.array_equal(f, _oracle(oracle, p, f0s[3], 10, None)[0])
