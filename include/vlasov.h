@@ -152,6 +152,24 @@ size_t vlasov_workspace_bytes(const vlasov_params *p);
 int vlasov_init(const vlasov_params *p, const double *f0_host, void *f_dev, void *ws_dev, void *hip_stream,
                 vlasov_ctx **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * vlasov_init, but the workspace is the library's static device array of
+ * 16 MiB (one per device, held from its first use until the process ends)
+ * instead of a caller buffer; the caller still passes f0_host and the f pair
+ * f_dev (memory of the current device).  The call allocates nothing: no
+ * hipMalloc, hipFree or other allocating routine.  It rejects parameters
+ * whose vlasov_workspace_bytes() exceed 16 MiB with VLASOV_E_INVAL (every grid
+ * up to 4096 x 4096 fits; 8192 x 4096 does not).  One context per device may
+ * hold the array at a time: a second vlasov_init_static on the same device
+ * before vlasov_destroy of the first returns VLASOV_E_STATE (two contexts on
+ * one array would race).  Everything the step reads is rewritten at init, so
+ * the contents left by an earlier context do not matter.  Errors otherwise as
+ * vlasov_init; VLASOV_E_INVAL also if f_dev is not memory of the current
+ * device. */
+int vlasov_init_static(const vlasov_params *p, const double *f0_host, void *f_dev, void *hip_stream,
+                       vlasov_ctx **out);
+
 /* EXTERNAL model only: set the force F(x_i), nx FP64 values (copied).
  * VLASOV_E_STATE on other models. */
 int vlasov_set_external_force(vlasov_ctx *c, const double *F_host);

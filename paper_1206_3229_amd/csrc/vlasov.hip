@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "vlasov_internal.hpp"
 
@@ -16,6 +17,22 @@ using namespace vlasov_detail;
 namespace {
 thread_local std::string g_err;
 }
+
+// Workspace of the contexts made by vlasov_init_static, for callers that
+// cannot allocate device memory.  Each device the library runs on holds its
+// own copy until the process ends.  Host code never passes the name of the
+// array to a kernel or a copy (there it is a host-side stand-in): the device
+// address comes from hipGetSymbolAddress, once per device, and only that
+// address is used.
+constexpr size_t STATIC_WS_MAX = (size_t)16 << 20;
+static __device__ __align__(256) char scratch[STATIC_WS_MAX];
+
+namespace {
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[STATIC_MAX_DEVICES];   // device address of `scratch` per device
+bool g_static_busy[STATIC_MAX_DEVICES];   // a live context holds that device's copy
+}  // namespace
 
 namespace vlasov_detail {
 
@@ -504,6 +521,50 @@ int vlasov_init(const vlasov_params *p, const double *f0_host, void *f_dev, void
     return VLASOV_OK;
 }
 
+int vlasov_init_static(const vlasov_params *p, const double *f0_host, void *f_dev, void *hip_stream,
+                       vlasov_ctx **out)
+{
+    std::string why = validate(p);
+    if (!why.empty()) return fail(VLASOV_E_INVAL, why);
+    if (!f_dev || !out) return fail(VLASOV_E_INVAL, "NULL pointer argument");
+    const size_t wb = layout_of(*p).total;
+    if (wb > STATIC_WS_MAX)
+        return fail(VLASOV_E_INVAL, "workspace of " + std::to_string(wb) + " bytes exceeds the static maximum of " +
+                                        std::to_string(STATIC_WS_MAX) + " bytes (use vlasov_init)");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= STATIC_MAX_DEVICES) return fail(VLASOV_E_INVAL, "device ordinal out of range");
+    hipPointerAttribute_t attr{};
+    if (hipPointerGetAttributes(&attr, f_dev) != hipSuccess || attr.device != dev) {
+        (void)hipGetLastError();
+        return fail(VLASOV_E_INVAL, "f_dev is not device memory of the current device");
+    }
+    void *ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static_busy[dev])
+            return fail(VLASOV_E_STATE, "the static workspace of device " + std::to_string(dev) +
+                                            " is held by a live context (destroy it first)");
+        if (!g_static_ptr[dev]) {
+            void *ptr = nullptr;
+            hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr)
+                return fail(VLASOV_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            g_static_ptr[dev] = ptr;
+        }
+        ws = g_static_ptr[dev];
+        g_static_busy[dev] = true;
+    }
+    const int rc = vlasov_init(p, f0_host, f_dev, ws, hip_stream, out);
+    if (rc != VLASOV_OK) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        g_static_busy[dev] = false;
+        return rc;
+    }
+    (*out)->static_dev = dev;
+    return VLASOV_OK;
+}
+
 int vlasov_set_external_force(vlasov_ctx *c, const double *F_host)
 {
     if (!c || !F_host) return fail(VLASOV_E_INVAL, "NULL argument");
@@ -702,6 +763,10 @@ int vlasov_destroy(vlasov_ctx *c)
     for (auto e : c->pool) (void)hipEventDestroy(e);
     drop_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        g_static_busy[c->static_dev] = false;
+    }
     delete c;
     return VLASOV_OK;
 }

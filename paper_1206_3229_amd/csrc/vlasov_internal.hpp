@@ -79,6 +79,8 @@ struct vlasov_ctx {
     int64_t nblk;
     bool have_force;
     vlasov_tuning tune;  // launch shapes of the drift and kick
+    // device whose static workspace this context holds (vlasov_init_static), or -1
+    int static_dev = -1;
     // HIP graphs of gsteps whole steps (vlasov_set_graph; 0: none), captured on
     // cap_stream the first time they are needed, one per current buffer at the
     // start

@@ -104,6 +104,7 @@ def load() -> C.CDLL:
             "vlasov_f_bytes": (C.c_size_t, [P]),
             "vlasov_workspace_bytes": (C.c_size_t, [P]),
             "vlasov_init": (C.c_int, [P, _D, V, V, V, C.POINTER(V)]),
+            "vlasov_init_static": (C.c_int, [P, _D, V, V, C.POINTER(V)]),
             "vlasov_set_external_force": (C.c_int, [V, _D]),
             "vlasov_step": (C.c_int, [V, C.c_int64]),
             "vlasov_set_graph": (C.c_int, [V, C.c_int32]),
@@ -172,9 +173,14 @@ def _torch():
 
 
 class Solver:
-    """One simulation: f pair and workspace in device memory, steps on the current stream."""
+    """One simulation: f pair and workspace in device memory, steps on the current stream.
 
-    def __init__(self, params, f0: np.ndarray, hist_cap: int = 0, device: int | None = None):
+    static_workspace=True creates the context with vlasov_init_static: the
+    workspace is the library's static device array (no workspace tensor), one
+    such context per device at a time."""
+
+    def __init__(self, params, f0: np.ndarray, hist_cap: int = 0, device: int | None = None,
+                 static_workspace: bool = False):
         torch = _torch()
         lib = load()
         self.params = params
@@ -186,7 +192,7 @@ class Solver:
             raise VlasovError(E_INVAL, "invalid parameters")
         with torch.cuda.device(self.device):
             self.f_buf = torch.empty(fb, dtype=torch.uint8, device=self.device)
-            self.ws_buf = torch.empty(wb, dtype=torch.uint8, device=self.device)
+            self.ws_buf = None if static_workspace else torch.empty(wb, dtype=torch.uint8, device=self.device)
             self.stream = torch.cuda.current_stream(self.device)
         # f0: the initial f as an FP64 [np][nx] array, or an IC generated on the device
         gen = f0 if isinstance(f0, IC) else None
@@ -196,9 +202,14 @@ class Solver:
                 raise ValueError(f"f0 shape {f0.shape} != (np, nx) = {(params.np_, params.nx)}")
         f0p = None if gen is not None else _dptr(f0)
         ctx = C.c_void_p()
-        check(lib.vlasov_init(C.byref(self._p), f0p, C.c_void_p(self.f_buf.data_ptr()),
-                              C.c_void_p(self.ws_buf.data_ptr()), C.c_void_p(self.stream.cuda_stream),
-                              C.byref(ctx)))
+        if static_workspace:
+            with torch.cuda.device(self.device):
+                check(lib.vlasov_init_static(C.byref(self._p), f0p, C.c_void_p(self.f_buf.data_ptr()),
+                                             C.c_void_p(self.stream.cuda_stream), C.byref(ctx)))
+        else:
+            check(lib.vlasov_init(C.byref(self._p), f0p, C.c_void_p(self.f_buf.data_ptr()),
+                                  C.c_void_p(self.ws_buf.data_ptr()), C.c_void_p(self.stream.cuda_stream),
+                                  C.byref(ctx)))
         self._ctx = ctx
         self.nx, self.np_ = params.nx, params.np_
         if gen is not None:
