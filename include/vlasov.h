@@ -277,12 +277,14 @@ typedef struct {
     int32_t drift_threads;     /* threads per drift workgroup: 64, 128 or 256 (2 columns each) */
     int32_t kick_rows;         /* rows per thread of the kick: 8, 16 or 32 */
     int32_t kick_drift_width;  /* 0: the kick (step 3) and the two half drifts after it (step 4
-                                  and the next step 1) run as separate kernels; 256 or 512: one
-                                  fused kernel on tiles of that many columns, which reads and
-                                  writes f once for both sweeps.  It is used where the drift
-                                  shifts of the rows of every tile differ by at most 4 columns,
-                                  else the separate kernels run.  The last step of a call
-                                  (kick and one half drift) always uses the separate kernels. */
+                                  and the next step 1) run as separate kernels; 230 or 486: one
+                                  fused kernel on tiles of that many columns (four or eight
+                                  wavefronts: the 256 or 512 columns a tile kicks, one per
+                                  thread), which reads and writes f once for the three sweeps.
+                                  It is used where the combined drift offsets of the rows of
+                                  every tile differ by at most 8 columns, else the separate
+                                  kernels run.  The last step of a call (kick and one half
+                                  drift) always uses the separate kernels. */
     int32_t kick_drift_blocks; /* rows of a fused tile in 16-row density blocks: 1, 2 or 4 */
 } vlasov_tuning;
 

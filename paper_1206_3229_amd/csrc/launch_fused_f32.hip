@@ -54,7 +54,7 @@ int launch_kick_drift_w(vlasov_ctx *c, int ta, double h)
 // and (tb >= 0, then with partial sums) that of table tb = k + 1 mod nsub:
 // the fused kernel where the tables allow it and the launch shape asks for
 
-template int launch_kick_drift_w<float, 256>(vlasov_ctx *, int, double);
-template int launch_kick_drift_w<float, 512>(vlasov_ctx *, int, double);
+template int launch_kick_drift_w<float, 230>(vlasov_ctx *, int, double);
+template int launch_kick_drift_w<float, 486>(vlasov_ctx *, int, double);
 
 }  // namespace vlasov_detail

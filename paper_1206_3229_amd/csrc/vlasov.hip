@@ -227,8 +227,8 @@ int kick_then_drift(vlasov_ctx *c, int k, int tb, double h, bool filt)
     const int w = c->tune.kick_drift_width;
     if (tb >= 0 && !filt && w != 0 && c->kd_ok[k] && c->P.spline == VLASOV_SPLINE_FD) {
         const bool f32 = c->P.storage == VLASOV_F32;
-        if (w == 256) return f32 ? launch_kick_drift_w<float, 256>(c, k, h) : launch_kick_drift_w<double, 256>(c, k, h);
-        return f32 ? launch_kick_drift_w<float, 512>(c, k, h) : launch_kick_drift_w<double, 512>(c, k, h);
+        if (w == 230) return f32 ? launch_kick_drift_w<float, 230>(c, k, h) : launch_kick_drift_w<double, 230>(c, k, h);
+        return f32 ? launch_kick_drift_w<float, 486>(c, k, h) : launch_kick_drift_w<double, 486>(c, k, h);
     }
     int rc = filt ? kick_filter(c, h) : kick(c, h);
     if (rc == VLASOV_OK) rc = drift(c, k, tb, tb >= 0);
@@ -775,7 +775,7 @@ int vlasov_tuning_candidates(vlasov_tuning *out, int32_t cap, int32_t *n)
 {
     static const int nts[] = {64, 128, 256}, rs[] = {8, 16, 32};
     if (!n || cap < 0 || (cap > 0 && !out)) return fail(VLASOV_E_INVAL, "bad argument");
-    static const int kdw[] = {256, 512}, kdb[] = {1, 2, 4};
+    static const int kdw[] = {230, 486}, kdb[] = {1, 2, 4};
     int k = 0;
     for (int a : nts)
         for (int r : rs) {
@@ -798,7 +798,7 @@ int vlasov_set_tuning(vlasov_ctx *c, const vlasov_tuning *t)
     if (!c || !t) return fail(VLASOV_E_INVAL, "NULL argument");
     const bool nt_ok = t->drift_threads == 64 || t->drift_threads == 128 || t->drift_threads == 256;
     const bool r_ok = t->kick_rows == 8 || t->kick_rows == 16 || t->kick_rows == 32;
-    const bool w_ok = t->kick_drift_width == 0 || t->kick_drift_width == 256 || t->kick_drift_width == 512;
+    const bool w_ok = t->kick_drift_width == 0 || t->kick_drift_width == 230 || t->kick_drift_width == 486;
     const bool b_ok = t->kick_drift_blocks == 1 || t->kick_drift_blocks == 2 || t->kick_drift_blocks == 4;
     if (!nt_ok || !r_ok || !w_ok || !b_ok) return fail(VLASOV_E_INVAL, "launch shape not compiled in");
     const bool retable = t->kick_drift_blocks != c->kd_rb;

@@ -46,7 +46,7 @@ bool fusable(const vlasov_ctx *c)
     return c->kd_ok[0] && c->kd_rb == 1 && c->P.bc_p == VLASOV_BC_PERIODIC;
 }
 
-int kd_tiles(const vlasov_ctx *c) { return (int)((c->P.nx + 255) / 256) * (int)c->nblk; }
+int kd_tiles(const vlasov_ctx *c) { return (int)((c->P.nx + vk::KB_KD_TW - 1) / vk::KB_KD_TW) * (int)c->nblk; }
 
 int drift_tiles(const vlasov_ctx *c)
 {
@@ -243,7 +243,7 @@ class Engine {
             vk::kb_density<<<KB_DENS_WG, 256, 0, st>>>(gd, cy + k);
             vk::kb_force<<<KB_FORCE_WG, KB_FORCE_NT, 0, st>>>(gd, cy + k);
             vk::kb_kick<T, kick_rows<T>()><<<KB_KICK_WG, 256, 0, st>>>(gd, cy + k);
-            if (fuse_) vk::kb_kick_drift<T, kd_pf<T>()><<<KB_KD_WG, vk::KDGeom<256>::NT, 0, st>>>(gd, cy + k);
+            if (fuse_) vk::kb_kick_drift<T, kd_pf<T>()><<<KB_KD_WG, vk::KDGeom<vk::KB_KD_TW>::NT, 0, st>>>(gd, cy + k);
         }
     }
 

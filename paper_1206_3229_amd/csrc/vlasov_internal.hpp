@@ -35,8 +35,8 @@ constexpr int DRIFT_NT = 128, DRIFT_V = 2, DRIFT_PF = 4;
 template <typename T> constexpr int kick_rows() { return sizeof(T) == 8 ? 16 : 32; }
 // fused kick and drift: default tile width and blocks; rows requested ahead
 // by the kick (FP64 within 96 VGPRs, five waves per SIMD)
-constexpr int KD_TW = 256, KD_RB = 1;
-template <typename T> constexpr int kd_pf() { return 4; }
+constexpr int KD_TW = 230, KD_RB = 1;
+template <typename T> constexpr int kd_pf() { return 2; }
 // rows per thread of the filter along p
 constexpr int FILTER_R = 16;
 // substeps of a step at most (the splittings of vlasov_splitting)

@@ -583,52 +583,69 @@ static __global__ __launch_bounds__(256) void k_kick_filter(const T *__restrict_
 // ---------------------------------------------------------------------------
 constexpr int KD_SPR = 8;
 
+// Geometry of a fused tile of TW columns: runs of two adjacent values per lane
+// in both half drifts (16-byte LDS accesses, conflict-free), W1 waves for the
+// first half drift (TW + 9 values per row) and W2 for the second (TW outputs),
+// one kicked column per lane over the KW = TW + 18 + SPR columns the windows
+// need.  Every wave kicks; TW = 230 (four waves) and 486 (eight) make the
+// kicked columns and both half drifts fill their waves.
 template <int TW>
 struct KDGeom {
-    static constexpr int V1 = 5, V2 = 4;                  // outputs per lane in the two half drifts
-    static constexpr int MIDN = TW + 9;                   // first-pass values per row
-    static constexpr int NRUN1 = (MIDN + V1 - 1) / V1;    // first-pass lanes
-    static constexpr int NRUN2 = (TW + V2 - 1) / V2;      // second-pass lanes
+    static constexpr int V = 2;                          // outputs per lane in the half drifts
+    static constexpr int MIDN = TW + 9;                  // first-pass values per row
+    static constexpr int NRUN1 = (MIDN + V - 1) / V;     // first-pass lanes
+    static constexpr int NRUN2 = TW / V;                 // second-pass lanes
     static constexpr int W1 = (NRUN1 + 63) / 64, W2 = (NRUN2 + 63) / 64;
-    static constexpr int KW = TW + 18 + KD_SPR;           // kicked columns per row
-    static constexpr int NT = (KW + 63) / 64 * 64;        // one kicked column per lane
-    static constexpr int KLD = NT;                        // kicked-row buffer (slot = lane)
-    static constexpr int MLD = (NRUN1 * V1 + 3) / 4 * 4;  // first-pass row buffer
-    static_assert(W1 + W2 <= NT / 64, "both half drifts have waves of their own");
-    static_assert(KD_SPR + (NRUN1 - 1) * V1 + V1 + 9 <= KLD, "first-pass reads stay in the kicked row");
-    static_assert((NRUN2 - 1) * V2 + V2 + 9 <= MIDN, "second-pass reads stay in the first-pass row");
-    static_assert(TW % V2 == 0, "whole second-pass runs");
+    static constexpr int KW = TW + 18 + KD_SPR;          // kicked columns per row
+    static constexpr int NWK = (KW + 63) / 64;
+    static constexpr int NW = NWK > W1 + W2 ? NWK : W1 + W2;  // waves
+    static constexpr int NT = 64 * NW;
+    // Role of wave w in a workgroup rotated by `rot`: roles [0, W1) run the
+    // first half drift, [W1, W1 + W2) the second.  Rotating the roles from one
+    // workgroup to the next spreads them over the SIMDs.
+    static __device__ __forceinline__ int role(int w, int rot) { return (w + NW - rot) % NW; }
+    // kicked row: column c of the range at slot c + (krel & 1), so that every
+    // row's window starts at an even slot; both buffers padded for the reads
+    // of the last runs (V + 10 values from slot V u)
+    static constexpr int KLD = NT + 16;
+    static constexpr int MLD = NRUN1 * V + 16;
+    static_assert(TW % V == 0, "whole second-pass runs");
+    static_assert(KD_SPR + 1 + V * (NRUN1 - 1) + V + 10 <= KLD, "first-pass reads stay in the kicked row");
+    static_assert(V * (NRUN2 - 1) + V + 10 <= MLD, "second-pass reads stay in the first-pass row");
 };
 
-// V outputs of a run from V + 9 samples x (x[4 + k] the start of output k's
-// cell): V + 1 stencils shared by the run.
-template <typename T, int V>
-__device__ __forceinline__ void spline_run_regs(const T (&x)[V + 9], T a, T b, T g, T d, T (&o)[V])
-{
-    T D[V + 1];
-#pragma unroll
-    for (int k = 0; k <= V; ++k) D[k] = second_diff(x + 4 + k);
-#pragma unroll
-    for (int k = 0; k < V; ++k) o[k] = spline(a, b, g, d, x[4 + k], x[5 + k], D[k], D[k + 1]);
-}
-
-template <typename T, int BCX, int BCP, int TW, int PF, int RB, bool FULL>
+// P2: the calling wave runs the second half drift (and stores); the other
+// waves run the first half drift (or only kick).  The two roles are separate
+// code, so that the wait of each for its requested kick samples counts only
+// its own memory operations.
+template <typename T, int BCX, int BCP, int TW, int PF, int RB, bool FULL, bool P2>
 __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__restrict__ fout,
                                                 const double *__restrict__ F, double dt, double dp,
                                                 const int32_t *__restrict__ dm2, const double4 *__restrict__ dw1,
                                                 const double4 *__restrict__ dw2, const int32_t *__restrict__ kbase,
                                                 const int32_t *__restrict__ krel, double *__restrict__ part, int nx,
-                                                int np, int tx, int ty, T *kbuf, T *mbuf)
+                                                int np, int tx, int ty, int rw, T *kbuf, T *mbuf)
 {
     using G = KDGeom<TW>;
-    constexpr int V1 = G::V1, V2 = G::V2, R = ROWS_PER_BLOCK, KLD = G::KLD, MLD = G::MLD;
+    using V2 = typename Vec2<T>::type;
+    constexpr int V = G::V, R = ROWS_PER_BLOCK, KLD = G::KLD, MLD = G::MLD;
     constexpr int NS = R + 10 + PF;  // window slots: samples of a block plus those requested ahead
     static_assert(NS <= 32, "one mask bit per sample");
     const int t = threadIdx.x;
-    const int wave = t >> 6;
+    const int lane = t & 63;
     const int i0 = tx * TW;
     const int j0 = ty * (R * RB);
     const int nr = FULL ? R * RB : min(R * RB, np - j0);  // rows of the tile
+
+    // padding of the row buffers (read only by values that are never kept)
+    for (int s = G::NT + t; s < KLD; s += G::NT) {
+        kbuf[s] = T(0);
+        kbuf[KLD + s] = T(0);
+    }
+    for (int s = G::NRUN1 * V + t; s < MLD; s += G::NT) {
+        mbuf[s] = T(0);
+        mbuf[MLD + s] = T(0);
+    }
 
     // The kicked column of this lane: foot of its p shift (eq. step3), the
     // spline weights, and the element index of its first sample.
@@ -643,7 +660,7 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
         colin = c >= 0 && c < nx;
     }
     // every kicked column lies inside the grid (or the axis is periodic): no mask
-    const bool kick_in = BCX == BC_PERIODIC || (cL >= 0 && cL + G::KW <= nx);
+    const bool kick_in = BCX == BC_PERIODIC || (cL >= 0 && cL + G::NT <= nx);
     const Foot ft = foot_of_shift((F[gc] * dt) / dp);
     const int m = reduce_offset(ft.m, np, BCP);
     const T ka = (T)ft.a, kb = (T)ft.b, kg = (T)ft.g, kd = (T)ft.d;
@@ -679,118 +696,79 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
     for (int s = 0; s < 9; ++s) settle(s);
     T Dk = second_diff(w + 4);
 
-    const bool pass1 = wave < G::W1;
-    const bool pass2 = wave >= G::W1 && wave < G::W1 + G::W2;
-    const int u1 = t, u2 = t - 64 * G::W1;  // run of the lane in its pass
-    const int i = i0 + V2 * u2;             // first output column of a second-pass lane
-    const bool own2 = pass2 && u2 < G::NRUN2 && (FULL || i < nx);
+    const bool pass1 = !P2 && rw < G::W1;
+    const int u1 = 64 * rw + lane, u2 = 64 * (rw - G::W1) + lane;  // run of the lane in its pass
+    const int i = i0 + V * u2;  // first output column of a second-pass lane
+    const bool own2 = P2 && u2 < G::NRUN2 && i < nx;
     const bool own1 = pass1 && u1 < G::NRUN1;
 
     for (int blk = 0; blk < RB; ++blk) {
         const int jb = j0 + R * blk;
         if (!FULL && R * blk >= nr) break;  // uniform
-        double acc[V2];
+        double acc[V];
 #pragma unroll
-        for (int k = 0; k < V2; ++k) acc[k] = 0.0;
+        for (int k = 0; k < V; ++k) acc[k] = 0.0;
 #pragma unroll
         for (int r = 0; r < R + 2; ++r) {
             if (r < R && (FULL || R * blk + r < nr)) {
-                // kick of row r into slot t of its buffer
+                // kick of row r into its buffer
                 settle(r + 9);
                 const T Dk1 = second_diff(w + r + 5);
                 T y = spline(ka, kb, kg, kd, w[r + 4], w[r + 5], Dk, Dk1);
                 Dk = Dk1;
                 if (!kick_in) y = colin ? y : T(0);
-                kbuf[(r & 1) * KLD + t] = y;
+                kbuf[(r & 1) * KLD + (krel[jb + r] & 1) + t] = y;
                 // samples of the next block are requested too (the last
                 // block's extra requests read valid rows and are unused)
                 if (r + 10 + PF < NS && (RB > 1 || r + 10 + PF < R + 10)) request(r + 10 + PF);
             }
-            if (r >= 1 && r - 1 < R && (FULL || R * blk + r - 1 < nr) && own1) {
+            if (!P2 && r >= 1 && r - 1 < R && (FULL || R * blk + r - 1 < nr) && own1) {
                 // first half drift (table 1) of row r - 1 at the positions
                 // i0 + m2 - 4 + q, q in [0, TW + 9), that the second reads
                 const int q1 = r - 1, j = jb + q1;
-                const T *src = kbuf + (q1 & 1) * KLD + krel[j] + V1 * u1;
+                const int rel = krel[j];
+                const T *src = kbuf + (q1 & 1) * KLD + rel + (rel & 1);
                 const double4 w1 = dw1[j];
-                T x[V1 + 9], o[V1];
-#pragma unroll
-                for (int k = 0; k < V1 + 9; ++k) x[k] = src[k];
-                spline_run_regs<T, V1>(x, (T)w1.x, (T)w1.y, (T)w1.z, (T)w1.w, o);
+                T o[V];
+                spline_run<T, V>(src, u1, (T)w1.x, (T)w1.y, (T)w1.z, (T)w1.w, o);
                 if (BCX == BC_ZERO) {
                     const int lo = i0 + dm2[j] - 4;  // position of first-pass value 0
                     if (!(lo >= 0 && lo + G::MIDN <= nx)) {
-                        const int q = lo + V1 * u1;
+                        const int q = lo + V * u1;
 #pragma unroll
-                        for (int k = 0; k < V1; ++k)
+                        for (int k = 0; k < V; ++k)
                             if (q + k < 0 || q + k >= nx) o[k] = T(0);
                     }
                 }
-                T *dst = mbuf + (q1 & 1) * MLD + V1 * u1;
-#pragma unroll
-                for (int k = 0; k < V1; ++k) dst[k] = o[k];
+                V2 ww;
+                ww.x = o[0];
+                ww.y = o[1];
+                reinterpret_cast<V2 *>(mbuf + (q1 & 1) * MLD)[u1] = ww;
             }
-            if (r >= 2 && (FULL || R * blk + r - 2 < nr) && own2) {
-                // second half drift (table 2) of row r - 2: outputs i .. i + 3
+            if (P2 && r >= 2 && (FULL || R * blk + r - 2 < nr) && own2) {
+                // second half drift (table 2) of row r - 2: outputs i, i + 1
                 const int q2 = r - 2, j = jb + q2;
-                const T *src = mbuf + (q2 & 1) * MLD + V2 * u2;
                 const double4 wd = dw2[j];
-                T x[V2 + 9], o[V2];
-                using V4 = typename Vec4<T>::type;
-                using VV2 = typename Vec2<T>::type;
-                if constexpr (sizeof(T) == 8) {
-#pragma unroll
-                    for (int k = 0; k < 6; ++k) {
-                        const VV2 v = reinterpret_cast<const VV2 *>(src)[k];
-                        x[2 * k] = v.x;
-                        x[2 * k + 1] = v.y;
-                    }
-                    x[12] = src[12];
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const V4 v = reinterpret_cast<const V4 *>(src)[k];
-                        x[4 * k] = v.x;
-                        x[4 * k + 1] = v.y;
-                        x[4 * k + 2] = v.z;
-                        x[4 * k + 3] = v.w;
-                    }
-                    x[12] = src[12];
-                }
-                spline_run_regs<T, V2>(x, (T)wd.x, (T)wd.y, (T)wd.z, (T)wd.w, o);
-                T *row = fout + (size_t)j * nx;
+                T o[V];
+                spline_run<T, V>(mbuf + (q2 & 1) * MLD, u2, (T)wd.x, (T)wd.y, (T)wd.z, (T)wd.w, o);
                 if (FULL) {
-                    if constexpr (sizeof(T) == 8) {
-                        VV2 *p = reinterpret_cast<VV2 *>(row + i);
-                        VV2 a, b;
-                        a.x = o[0];
-                        a.y = o[1];
-                        b.x = o[2];
-                        b.y = o[3];
-                        p[0] = a;
-                        p[1] = b;
-                    } else {
-                        V4 a;
-                        a.x = o[0];
-                        a.y = o[1];
-                        a.z = o[2];
-                        a.w = o[3];
-                        *reinterpret_cast<V4 *>(row + i) = a;
-                    }
+                    V2 ww;
+                    ww.x = o[0];
+                    ww.y = o[1];
+                    *reinterpret_cast<V2 *>(fout + (size_t)j * nx + i) = ww;
                 } else {
-#pragma unroll
-                    for (int k = 0; k < V2; ++k)
-                        if (i + k < nx) row[i + k] = o[k];
+                    store_run<T, V>(fout + (size_t)j * nx, i, nx, o);
                 }
 #pragma unroll
-                for (int k = 0; k < V2; ++k) acc[k] = acc[k] + (double)o[k];
+                for (int k = 0; k < V; ++k) acc[k] = acc[k] + (double)o[k];
             }
             __syncthreads();
         }
-        if (own2) {
+        if (P2 && own2) {
             double *prow = part + (size_t)(ty * RB + blk) * nx;
 #pragma unroll
-            for (int k = 0; k < V2; ++k)
-                if (FULL || i + k < nx) prow[i + k] = acc[k];
+            for (int k = 0; k < V; ++k)
+                if (i + k < nx) prow[i + k] = acc[k];
         }
         // slide the window by one block: sample s + 16 becomes sample s
         if (RB > 1) {
@@ -802,7 +780,6 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
     }
 }
 
-// FP64: at most 96 VGPRs (five waves per SIMD); FP32 at most 80 (six).
 template <typename T, int BCX, int BCP, int TW, int PF, int RB>
 static __global__ __launch_bounds__(KDGeom<TW>::NT) void k_kick_drift(
     const T *__restrict__ fin, T *__restrict__ fout, const double *__restrict__ F, double dt, double dp,
@@ -815,14 +792,26 @@ static __global__ __launch_bounds__(KDGeom<TW>::NT) void k_kick_drift(
     __shared__ __attribute__((aligned(16))) T mbuf[2 * G::MLD];  // two first-pass rows
     int tx, ty;
     if (!xcd_tile(ntx, nty, tx, ty)) return;
-    constexpr int VA = sizeof(T) == 8 ? 2 : 4;  // vector stores need rows aligned to VA values
-    const bool full = (ty + 1) * (ROWS_PER_BLOCK * RB) <= np && (tx + 1) * TW <= nx && nx % VA == 0;
-    if (full)
-        kick_drift_tile<T, BCX, BCP, TW, PF, RB, true>(fin, fout, F, dt, dp, dm2, dw1, dw2, kbase, krel, part, nx,
-                                                       np, tx, ty, kbuf, mbuf);
-    else
-        kick_drift_tile<T, BCX, BCP, TW, PF, RB, false>(fin, fout, F, dt, dp, dm2, dw1, dw2, kbase, krel, part, nx,
-                                                        np, tx, ty, kbuf, mbuf);
+    // every row of the tile in the grid, and rows of an even length (aligned
+    // two-value stores)
+    const bool full = (ty + 1) * (ROWS_PER_BLOCK * RB) <= np && (nx & 1) == 0;
+    const int rw = G::role(threadIdx.x >> 6, blockIdx.x % G::NW);
+    const bool p2 = rw >= G::W1 && rw < G::W1 + G::W2;
+#define KDT(FL, P)                                                                                                  \
+    kick_drift_tile<T, BCX, BCP, TW, PF, RB, FL, P>(fin, fout, F, dt, dp, dm2, dw1, dw2, kbase, krel, part, nx, np, tx, \
+                                                    ty, rw, kbuf, mbuf)
+    if (full) {
+        if (p2)
+            KDT(true, true);
+        else
+            KDT(true, false);
+    } else {
+        if (p2)
+            KDT(false, true);
+        else
+            KDT(false, false);
+    }
+#undef KDT
 }
 
 // ---------------------------------------------------------------------------
@@ -1678,43 +1667,53 @@ static __global__ __launch_bounds__(256) void kb_kick(const GridDesc *__restrict
 }
 
 // The kick fused with the two half drifts after it (the second of one step,
-// the first of the next) for the members whose tables allow it: tiles of 256
+// the first of the next) for the members whose tables allow it: tiles of 230
 // columns by 16 rows, as the single-grid kernel.  Periodic p only.
+constexpr int KB_KD_TW = 230;
 template <typename T, int PF>
-static __global__ __launch_bounds__(KDGeom<256>::NT) void kb_kick_drift(const GridDesc *__restrict__ gd,
-                                                                        const Cycle *__restrict__ cy)
+static __global__ __launch_bounds__(KDGeom<KB_KD_TW>::NT) void kb_kick_drift(const GridDesc *__restrict__ gd,
+                                                                             const Cycle *__restrict__ cy)
 {
-    using G = KDGeom<256>;
+    using G = KDGeom<KB_KD_TW>;
     __shared__ __attribute__((aligned(16))) T kbuf[2 * G::KLD];
     __shared__ __attribute__((aligned(16))) T mbuf[2 * G::MLD];
-    constexpr int VA = sizeof(T) == 8 ? 2 : 4;
     const int n = cy->n;
     const int total = cy->off_kd[n];
     for (int e = blockIdx.x; e < total; e += gridDim.x) {
         const int a = find_member(cy->off_kd, n, e);
         const GridDesc &g = gd[cy->slot[a]];
         const int li = e - cy->off_kd[a];
-        const int ntx = (g.nx + 255) / 256;
+        const int ntx = (g.nx + KB_KD_TW - 1) / KB_KD_TW;
         const int tx = li % ntx, ty = li / ntx;
         const int kin = cy->kin[a];
         const T *fin = (const T *)g.f[kin];
         T *fout = (T *)g.f[kin ^ 1];
-        const bool full = (ty + 1) * ROWS_PER_BLOCK <= g.np && (tx + 1) * 256 <= g.nx && g.nx % VA == 0;
+        const bool full = (ty + 1) * ROWS_PER_BLOCK <= g.np && (g.nx & 1) == 0;
+        const int rw = G::role(threadIdx.x >> 6, e % G::NW);
+        const bool p2 = rw >= G::W1 && rw < G::W1 + G::W2;
         __syncthreads();  // the previous item's LDS rows are consumed
-#define KDB(BX, FL)                                                                                                  \
-    kick_drift_tile<T, BX, BC_PERIODIC, 256, PF, 1, FL>(fin, fout, g.Fkick, g.dt, g.dp, g.dm, g.dw, g.dw, g.kbase,      \
-                                                        g.krel, g.part, g.nx, g.np, tx, ty, kbuf, mbuf)
+#define KDB(BX, FL, P)                                                                                               \
+    kick_drift_tile<T, BX, BC_PERIODIC, KB_KD_TW, PF, 1, FL, P>(fin, fout, g.Fkick, g.dt, g.dp, g.dm, g.dw, g.dw,         \
+                                                                g.kbase, g.krel, g.part, g.nx, g.np, tx, ty, rw, kbuf, mbuf)
+#define KDB2(BX, FL)     \
+    if (p2)              \
+        KDB(BX, FL, true); \
+    else                 \
+        KDB(BX, FL, false)
         if (g.bc_x == BC_PERIODIC) {
-            if (full)
-                KDB(BC_PERIODIC, true);
-            else
-                KDB(BC_PERIODIC, false);
+            if (full) {
+                KDB2(BC_PERIODIC, true);
+            } else {
+                KDB2(BC_PERIODIC, false);
+            }
         } else {
-            if (full)
-                KDB(BC_ZERO, true);
-            else
-                KDB(BC_ZERO, false);
+            if (full) {
+                KDB2(BC_ZERO, true);
+            } else {
+                KDB2(BC_ZERO, false);
+            }
         }
+#undef KDB2
 #undef KDB
     }
 }

@@ -270,7 +270,7 @@ class Solver:
 
     # -- launch shapes ---------------------------------------------------
     def set_tuning(self, drift_threads: int, kick_rows: int, kick_drift_width: int = 0, kick_drift_blocks: int = 1):
-        """kick_drift_width 0: separate kick and drift kernels; 256 or 512:
+        """kick_drift_width 0: separate kick and drift kernels; 230 or 486:
         the fused kernel on tiles of that width and kick_drift_blocks 16-row
         blocks (where the grid allows it)."""
         t = Tuning(int(drift_threads), int(kick_rows), int(kick_drift_width), int(kick_drift_blocks))

@@ -22,15 +22,15 @@ def test_algorithmic_bytes_per_point():
 def test_measured_traffic_only_for_the_current_sources(tmp_path, monkeypatch):
     prof = tmp_path / "profiles"
     prof.mkdir()
-    line = "kernel kick_drift2 shape 128/16/256/1: hbm_bytes_per_launch=3.25e+08"
+    line = "kernel kick_drift2 shape 128/16/230/1: hbm_bytes_per_launch=3.25e+08"
     (prof / "pmc_w.txt").write_text(f"kernel_source_hash: {bench.kernel_source_hash()}\n{line}\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("w", "kick_drift2", (128, 16, 256, 1)) == 3.25e8
-    assert bench.measured_traffic("w", "kick_drift2", (128, 16, 512, 2)) is None
-    assert bench.measured_traffic("w", "kick", (128, 16, 256, 1)) is None
+    assert bench.measured_traffic("w", "kick_drift2", (128, 16, 230, 1)) == 3.25e8
+    assert bench.measured_traffic("w", "kick_drift2", (128, 16, 486, 2)) is None
+    assert bench.measured_traffic("w", "kick", (128, 16, 230, 1)) is None
     (prof / "pmc_w.txt").write_text(f"kernel_source_hash: 0000000000000000\n{line}\n")
-    assert bench.measured_traffic("w", "kick_drift2", (128, 16, 256, 1)) is None
-    assert bench.measured_traffic("absent", "kick_drift2", (128, 16, 256, 1)) is None
+    assert bench.measured_traffic("w", "kick_drift2", (128, 16, 230, 1)) is None
+    assert bench.measured_traffic("absent", "kick_drift2", (128, 16, 230, 1)) is None
 
 
 def test_more_than_one_gpu_is_refused():

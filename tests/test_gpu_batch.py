@@ -200,14 +200,14 @@ def test_every_launch_shape_gives_identical_results(V, oracle):
         f = s.read_f()
         s.close()
         assert np.array_equal(f, ref), shape
-    assert {c[2] for c in V.tuning_candidates()} == {0, 256, 512}
+    assert {c[2] for c in V.tuning_candidates()} == {0, 230, 486}
     s = V.Solver(p, f0)
     with pytest.raises(V.VlasovError):
         s.set_tuning(96, 16)
     with pytest.raises(V.VlasovError):
         s.set_tuning(128, 16, 384)
     with pytest.raises(V.VlasovError):
-        s.set_tuning(128, 16, 256, 3)
+        s.set_tuning(128, 16, 230, 3)
     s.close()
 
 

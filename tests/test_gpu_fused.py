@@ -13,7 +13,7 @@ from paper_1206_3229_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 # (kick_drift_width, kick_drift_blocks)
-SHAPES = ((0, 1), (256, 1), (256, 2), (256, 4), (512, 1), (512, 4))
+SHAPES = ((0, 1), (230, 1), (230, 2), (230, 4), (486, 1), (486, 4))
 
 
 @pytest.fixture(scope="module")
@@ -126,7 +126,7 @@ def test_fused_single_step_calls(V, oracle):
     p = _sheet(300, 40, dt=0.04)
     f0 = _ic(p)
     s = V.Solver(p, f0)
-    s.set_tuning(128, 16, 512, 2)
+    s.set_tuning(128, 16, 486, 2)
     s.profile(True)
     for _ in range(4):
         s.step(1)

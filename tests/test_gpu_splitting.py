@@ -72,7 +72,7 @@ def test_splitting_matches_oracle_bitwise(V, oracle, name, scheme):
     n = 5
     want, hist_want = oracle.run(p, f0, n, history=True)
     _log(f"splitting {scheme} {name}")
-    for shape in ((128, 16, 256, 1), (128, 16, 512, 2), (128, 16, 0, 1)):
+    for shape in ((128, 16, 230, 1), (128, 16, 486, 2), (128, 16, 0, 1)):
         got, hist, prof = _run(V, p, f0, [n], shape, hist=n * NSUB[scheme])
         assert np.array_equal(got, want), (name, scheme, shape, float(np.max(np.abs(got - want))))
         if p.model in (I.MODEL_HMF, I.MODEL_RING):
@@ -89,7 +89,7 @@ def test_substeps_fuse_where_the_tables_allow(V, oracle, scheme):
     # small shifts: every pair of consecutive half drifts fuses with its kick
     p = _with(CASES["hmf600x50_f32"], splitting=scheme)
     f0 = _ic(p)
-    got, _, prof = _run(V, p, f0, [4], (128, 16, 256, 1))
+    got, _, prof = _run(V, p, f0, [4], (128, 16, 230, 1))
     assert prof["kick_drift2"][1] == 4 * NSUB[scheme] - 1 and prof["kick"][1] == 1
     assert np.array_equal(got, oracle.run(p, f0, 4))
 
@@ -112,7 +112,7 @@ def test_filter_matches_oracle_bitwise(V, oracle, storage, bc_p, every):
     f0 = _ic(p, 3)
     want = oracle.run(p, f0, 7)
     _log(f"filter storage={storage} bc_p={bc_p} every={every}")
-    for shape in ((128, 16, 256, 1), (128, 16, 0, 1)):
+    for shape in ((128, 16, 230, 1), (128, 16, 0, 1)):
         got, _, prof = _run(V, p, f0, [7], shape)
         assert np.array_equal(got, want), (storage, bc_p, every, shape)
         assert prof["filter"][1] == 7 // every
