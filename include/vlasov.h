@@ -304,6 +304,19 @@ int vlasov_get_tuning(vlasov_ctx *c, vlasov_tuning *t);
 
 #define VLASOV_BATCH_MAX 64
 
+/* Flags of batched stepping and of the server (the `flags` arguments):
+ *   VLASOV_BATCH_GRAPH  capture the chunk's launches into a HIP graph once and
+ *                       replay it;
+ *   VLASOV_BATCH_FUSE   run each member's kick fused with the pair of half drifts
+ *                       after it (the single-grid fused kernel on 230-column
+ *                       tiles, for members whose drift offsets allow it and
+ *                       whose p axis is periodic): f is read and written once
+ *                       for the three sweeps.  Off by default: on the
+ *                       512-request serving trace it measured slower (each
+ *                       fused tile is a 16-row pipeline whose latency sets the
+ *                       time of every batched phase). */
+enum { VLASOV_BATCH_GRAPH = 1, VLASOV_BATCH_FUSE = 2 };
+
 /* Bytes of device scratch for batched stepping in chunks of chunk_cycles
  * cycles (grid descriptors and per-cycle work tables, two sets). */
 size_t vlasov_batch_scratch_bytes(int32_t chunk_cycles);
@@ -313,14 +326,14 @@ size_t vlasov_batch_scratch_bytes(int32_t chunk_cycles);
  * stream; grids may differ in size, model and dt.  Every phase (drift,
  * density, force, kick) of all grids is one persistent launch whose
  * workgroups stride over the tiles of all grids; chunk_cycles cycles are
- * planned at a time and, with use_graph, captured once into a HIP graph and
- * replayed.  Each grid's result is bit-identical to vlasov_step on it alone.
+ * planned at a time and enqueued (flags: VLASOV_BATCH_*).  Each grid's result
+ * is bit-identical to vlasov_step on it alone.
  * Batches run the local spline with the Strang splitting and no filter.
  * scratch_dev: vlasov_batch_scratch_bytes(chunk_cycles) bytes, 256-aligned.
  * Synchronises the stream before returning.  VLASOV_E_INVAL for mismatched
  * contexts or a short scratch buffer. */
 int vlasov_batch_step(vlasov_ctx *const *ctxs, int32_t n, const int64_t *nsteps, void *scratch_dev,
-                      size_t scratch_bytes, int32_t chunk_cycles, int32_t use_graph);
+                      size_t scratch_bytes, int32_t chunk_cycles, int32_t flags);
 
 /* ---------------------------------------------------------------------------
  * Serving: a request loop over parameter-scan simulations of uneven sizes with
@@ -359,11 +372,13 @@ size_t vlasov_server_table_bytes(int32_t chunk_cycles);
 
 /* Create a server over the caller's device arena (256-aligned, kept until
  * destroy).  storage: VLASOV_F32 or VLASOV_F64 for every request; max_slots
- * <= VLASOV_BATCH_MAX grids run at once; chunk_cycles cycles per chunk.  A
- * scheduler thread owns all GPU work, on hip_stream.  No HIP call is made
- * before the first request is admitted. */
+ * <= VLASOV_BATCH_MAX grids run at once; chunk_cycles cycles per chunk; flags
+ * VLASOV_BATCH_*.  A scheduler thread owns all GPU work: chunks on hip_stream,
+ * admissions (tables and generated initial conditions) and retirements
+ * (diagnostics, final f) on two streams of its own, while the next chunk runs.
+ * No HIP call is made before the first request is admitted. */
 int vlasov_server_create(void *arena_dev, size_t arena_bytes, void *hip_stream, int32_t storage, int32_t max_slots,
-                         int32_t chunk_cycles, int32_t use_graph, vlasov_server **out);
+                         int32_t chunk_cycles, int32_t flags, vlasov_server **out);
 
 /* Queue a request (thread-safe, non-blocking).  f0_host: [np][nx] FP64,
  * copied, for r->ic.kind == VLASOV_IC_HOST; ignored (may be NULL) otherwise.

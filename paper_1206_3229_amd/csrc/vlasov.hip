@@ -161,8 +161,8 @@ int density_force(vlasov_ctx *c)
     const bool staged = nx <= vk::FORCE_LDS_MAX;
     switch (P.model) {
     case VLASOV_MODEL_HMF:
-        launch(c, VLASOV_K_FORCE, staged ? vk::k_force_hmf<true> : vk::k_force_hmf<false>, dim3(1), dim3(1024), rho,
-               cs, sn, F, nx, c->dx, mxmy, hist, hcount, P.hist_cap);
+        launch(c, VLASOV_K_FORCE, vk::k_force_hmf, dim3(1), dim3(1024), rho, cs, sn, F, nx, c->dx, mxmy, hist, hcount,
+               P.hist_cap);
         break;
     case VLASOV_MODEL_RING:
         launch(c, VLASOV_K_FORCE, staged ? vk::k_magnetization<true> : vk::k_magnetization<false>, dim3(1),

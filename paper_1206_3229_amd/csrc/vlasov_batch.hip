@@ -109,8 +109,10 @@ vk::GridDesc describe(const vlasov_ctx *c)
 // Plans and launches chunks of K cycles over a set of member grids.
 class Engine {
   public:
-    int init(char *dev, size_t bytes, hipStream_t st, int storage, int K, bool graph)
+    int init(char *dev, size_t bytes, hipStream_t st, int storage, int K, int flags)
     {
+        const bool graph = (flags & VLASOV_BATCH_GRAPH) != 0;
+        fuse_ = (flags & VLASOV_BATCH_FUSE) != 0;
         if (K < 1 || K > 4096) return fail(VLASOV_E_INVAL, "chunk_cycles must be in [1, 4096]");
         if (!dev || ((uintptr_t)dev % ALIGN) || bytes < 2 * set_bytes(K))
             return fail(VLASOV_E_INVAL, "batch scratch missing, misaligned or too small");
@@ -267,7 +269,7 @@ class Engine {
     hipGraphExec_t exec_[2] = {nullptr, nullptr};
     hipStream_t cap_ = nullptr;
     int set_ = 0;
-    bool fuse_ = true;  // the fused kick and drift pair for the members that allow it
+    bool fuse_ = false;  // the fused kick and drift pair for the members that allow it
 
   public:
     // failure handling tests: the chunk with this index (from 0) fails after
@@ -289,8 +291,13 @@ struct vlasov_server {
     char *arena = nullptr;
     size_t arena_bytes = 0, table_bytes = 0;
     hipStream_t stream = nullptr;
+    // admissions (tables, initial condition) and retirements (diagnostics,
+    // final f) run on streams of their own, beside the chunk on `stream`
+    hipStream_t adm = nullptr, ret = nullptr;
+    hipEvent_t cev[2] = {nullptr, nullptr};  // end of the last two chunks
+    int64_t chunk_seq = 0, completed = -1;   // chunks enqueued, last one known complete
     int storage = 0, max_slots = 0, K = 1;
-    bool graph = false;
+    int flags = 0;
     std::chrono::steady_clock::time_point t0;
 
     struct Pending {
@@ -313,6 +320,8 @@ struct vlasov_server {
         double t_submit, t_admit;
         int32_t failed = VLASOV_OK;  // error of the chunk this request was in
         int64_t closed_before = 0;   // steps finished before the current chunk
+        int64_t fin_chunk = -1;      // the chunk that finishes it (-1: none yet)
+        bool in_chunk = false;       // stepped by the chunk being enqueued
     };
 
     std::mutex mu;
@@ -394,11 +403,14 @@ void admit(vlasov_server *s)
         vlasov_ctx *c = nullptr;
         const bool gen = p.req.ic.kind != VLASOV_IC_HOST;
         int rc = vlasov_init(&p.req.p, gen ? nullptr : p.f0.data(), s->arena + off, s->arena + off + align_up(fb),
-                             s->stream, &c);
+                             s->adm, &c);
         if (rc == VLASOV_OK && gen && (rc = vlasov_generate_ic(c, &p.req.ic)) != VLASOV_OK) {
             vlasov_destroy(c);
             c = nullptr;
         }
+        // init and generation synchronised the admission stream; from now on
+        // the context's work is enqueued on the chunk stream
+        if (c) c->stream = s->stream;
         const double t_admit = seconds_since(s->t0);
         if (rc != VLASOV_OK) {
             vlasov_result r{};
@@ -427,14 +439,17 @@ void admit(vlasov_server *s)
 }
 
 // Retires finished members: diagnostics, optional final f, arena space back.
+// Retires the members whose last chunk is complete (diagnostics and the
+// final f on the retire stream, beside the chunk that may be running).
 void retire(vlasov_server *s)
 {
     std::vector<vlasov_server::Active> keep;
     for (auto &a : s->active) {
-        if (!a.m.done()) {
+        if (!a.m.done() || a.fin_chunk > s->completed) {
             keep.push_back(a);
             continue;
         }
+        a.ctx->stream = s->ret;
         vlasov_result r{};
         std::vector<double> f;
         if (a.failed != VLASOV_OK) {
@@ -483,7 +498,14 @@ void vlasov_server::run()
             dev_set = true;
         }
         if (!eng_ready) {
-            if (eng.init(arena, table_bytes, stream, storage, K, graph) != VLASOV_OK) {
+            int rc = eng.init(arena, table_bytes, stream, storage, K, flags);
+            if (rc == VLASOV_OK &&
+                (hipStreamCreateWithFlags(&adm, hipStreamNonBlocking) != hipSuccess ||
+                 hipStreamCreateWithFlags(&ret, hipStreamNonBlocking) != hipSuccess ||
+                 hipEventCreateWithFlags(&cev[0], hipEventDisableTiming) != hipSuccess ||
+                 hipEventCreateWithFlags(&cev[1], hipEventDisableTiming) != hipSuccess))
+                rc = fail(VLASOV_E_HIP, "server streams");
+            if (rc != VLASOV_OK) {
                 // fail every queued request
                 std::unique_lock<std::mutex> lk(mu);
                 const std::string why = vlasov_last_error();
@@ -504,26 +526,61 @@ void vlasov_server::run()
             std::this_thread::sleep_for(std::chrono::microseconds(200));
             continue;
         }
+        // One chunk ahead: chunk n is enqueued before the host waits for
+        // chunk n - 1 and retires the requests it finished, so the GPU runs
+        // while the host retires and admits.
         std::vector<Member *> ms;
         for (auto &a : active) {
+            a.in_chunk = !a.m.done();  // else finishing in an earlier chunk, or nothing to do
+            if (!a.in_chunk) continue;
             a.closed_before = a.m.closed;
             ms.push_back(&a.m);
         }
-        int rc = eng.chunk(ms);
-        if (rc == VLASOV_OK) {
-            const hipError_t e = hipStreamSynchronize(stream);
-            if (e != hipSuccess) rc = fail(VLASOV_E_HIP, std::string("chunk: ") + hipGetErrorString(e));
-        }
-        if (rc != VLASOV_OK) {
-            // the running requests fail with the chunk's error and leave
-            for (auto &a : active) {
-                a.failed = rc;
-                a.m.closed = a.m.total;
+        bool launched = false;
+        if (!ms.empty()) {
+            int rc = eng.chunk(ms);
+            if (rc == VLASOV_OK) {
+                const hipError_t e = hipEventRecord(cev[chunk_seq & 1], stream);
+                if (e != hipSuccess) rc = fail(VLASOV_E_HIP, std::string("chunk event: ") + hipGetErrorString(e));
             }
+            if (rc != VLASOV_OK) {
+                // the requests of this chunk fail with its error and leave
+                (void)hipStreamSynchronize(stream);
+                for (auto &a : active) {
+                    if (!a.in_chunk) continue;
+                    a.failed = rc;
+                    a.m.closed = a.m.total;
+                    a.fin_chunk = -1;
+                }
+                completed = chunk_seq - 1;
+            } else {
+                for (auto &a : active)
+                    if (a.m.done() && a.fin_chunk < 0 && a.closed_before < a.m.closed) a.fin_chunk = chunk_seq;
+                launched = true;
+            }
+            ++chunk_seq;
+        }
+        const int64_t want = launched ? chunk_seq - 2 : chunk_seq - 1;
+        if (want > completed) {
+            if (hipEventSynchronize(cev[want & 1]) != hipSuccess) {
+                (void)hipStreamSynchronize(stream);
+                // a device error: every running request fails and leaves
+                for (auto &a : active) {
+                    if (!a.m.done() || a.fin_chunk >= 0) a.failed = VLASOV_E_HIP;
+                    a.m.closed = a.m.total;
+                    a.fin_chunk = -1;
+                }
+            }
+            completed = want;
         }
         retire(this);
     }
+    if (chunk_seq > 0) (void)hipStreamSynchronize(stream);
     if (eng_ready) eng.release();
+    for (auto e : cev)
+        if (e) (void)hipEventDestroy(e);
+    if (adm) (void)hipStreamDestroy(adm);
+    if (ret) (void)hipStreamDestroy(ret);
 }
 
 extern "C" {
@@ -535,7 +592,7 @@ size_t vlasov_batch_scratch_bytes(int32_t chunk_cycles)
 }
 
 int vlasov_batch_step(vlasov_ctx *const *ctxs, int32_t n, const int64_t *nsteps, void *scratch_dev,
-                      size_t scratch_bytes, int32_t chunk_cycles, int32_t use_graph)
+                      size_t scratch_bytes, int32_t chunk_cycles, int32_t flags)
 {
     if (!ctxs || !nsteps || n < 1 || n > vk::BATCH_MAX) return fail(VLASOV_E_INVAL, "need 1..64 contexts");
     for (int a = 0; a < n; ++a) {
@@ -550,8 +607,7 @@ int vlasov_batch_step(vlasov_ctx *const *ctxs, int32_t n, const int64_t *nsteps,
             if (ctxs[b] == ctxs[a]) return fail(VLASOV_E_INVAL, "a context appears twice");
     }
     Engine eng;
-    int rc = eng.init((char *)scratch_dev, scratch_bytes, ctxs[0]->stream, ctxs[0]->P.storage, chunk_cycles,
-                      use_graph != 0);
+    int rc = eng.init((char *)scratch_dev, scratch_bytes, ctxs[0]->stream, ctxs[0]->P.storage, chunk_cycles, flags);
     if (rc != VLASOV_OK) {
         eng.release();
         return rc;
@@ -584,7 +640,7 @@ size_t vlasov_request_footprint(const vlasov_params *p)
 size_t vlasov_server_table_bytes(int32_t chunk_cycles) { return vlasov_batch_scratch_bytes(chunk_cycles); }
 
 int vlasov_server_create(void *arena_dev, size_t arena_bytes, void *hip_stream, int32_t storage, int32_t max_slots,
-                         int32_t chunk_cycles, int32_t use_graph, vlasov_server **out)
+                         int32_t chunk_cycles, int32_t flags, vlasov_server **out)
 {
     if (!arena_dev || !out || ((uintptr_t)arena_dev % ALIGN)) return fail(VLASOV_E_INVAL, "bad arena or output");
     if (storage != VLASOV_F64 && storage != VLASOV_F32) return fail(VLASOV_E_INVAL, "unknown storage");
@@ -600,7 +656,7 @@ int vlasov_server_create(void *arena_dev, size_t arena_bytes, void *hip_stream, 
     s->storage = storage;
     s->max_slots = max_slots;
     s->K = chunk_cycles;
-    s->graph = use_graph != 0;
+    s->flags = flags;
     if (const char *v = getenv("VLASOV_TEST_FAIL_CHUNK")) s->eng.fail_at_ = strtoll(v, nullptr, 10);
     s->t0 = std::chrono::steady_clock::now();
     s->free_[tb] = (arena_bytes - tb) / ALIGN * ALIGN;

@@ -1034,11 +1034,13 @@ __device__ __forceinline__ void density_block(const double *__restrict__ part, d
 
 // The same sums with 1024 threads: thread (c, g) forms the serial sum of
 // block class g alone, its loads (blocks g, g + 64, g + 128, g + 192 of a
-// round) all in flight at once.
+// round) all in flight at once; then wavefront c folds the 64 class sums of
+// column c with the xor butterfly (the same association as the pairwise tree
+// S[g] + S[g + d], d = 32, ..., 1: addition is commutative).
 static __global__ __launch_bounds__(1024) void k_density(const double *__restrict__ part, double *__restrict__ rho,
                                                   int nx, int nblk, double dp)
 {
-    __shared__ double S[64][17];
+    __shared__ double S[16][65];
     const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
     const int i = blockIdx.x * 16 + c;
     const int ic = min(i, nx - 1);
@@ -1055,13 +1057,12 @@ static __global__ __launch_bounds__(1024) void k_density(const double *__restric
         for (int k = 0; k < 4; ++k)
             if (b0 + g + 64 * k < nblk) acc = acc + x[k];
     }
-    S[g][c] = acc;
+    S[c][g] = acc;
     __syncthreads();
-    for (int d = 32; d >= 1; d >>= 1) {
-        if (g < d) S[g][c] = S[g][c] + S[g + d][c];
-        __syncthreads();
-    }
-    if (g == 0 && i < nx) rho[i] = dp * S[0][c];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double v = wave_sum(S[w][lane]);
+    const int io = blockIdx.x * 16 + w;
+    if (lane == 0 && io < nx) rho[io] = dp * v;
 }
 
 // Stage three arrays of n doubles into LDS (whole workgroup), the twelve
@@ -1175,15 +1176,27 @@ __device__ __forceinline__ void force_hmf_block(const double *__restrict__ rho, 
     for (int i = threadIdx.x; i < n; i += blockDim.x) F[i] = fma(my, c[i], -(mx * s[i]));
 }
 
-template <bool STAGED>
+// The single-grid form: wavefront 0 forms (M_x, M_y) from the arrays in
+// memory (the same chains as magnetization()), then every thread writes its
+// forces; no staging of the three arrays.
 static __global__ __launch_bounds__(1024) void k_force_hmf(const double *__restrict__ rho, const double *__restrict__ cs,
                                                     const double *__restrict__ sn, double *__restrict__ F, int n,
                                                     double dx, double *mxmy, double *hist, int64_t *hcount,
                                                     int64_t hcap)
 {
-    __shared__ double L[STAGED ? 3 * FORCE_LDS_MAX : 1];
     __shared__ double M[2];
-    force_hmf_block<STAGED>(rho, cs, sn, F, n, dx, mxmy, hist, hcount, hcap, L, M);
+    if (threadIdx.x < 64) {
+        double mx, my;
+        magnetization(rho, cs, sn, n, dx, mx, my);
+        if (threadIdx.x == 0) {
+            M[0] = mx;
+            M[1] = my;
+            record_history(mxmy, hist, hcount, hcap, mx, my);
+        }
+    }
+    __syncthreads();
+    const double mx = M[0], my = M[1];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) F[i] = fma(my, cs[i], -(mx * sn[i]));
 }
 
 // Magnetization only (ring model).  One workgroup, wavefront 0 reduces.

@@ -306,9 +306,13 @@ class Solver:
             pass
 
 
-def batch_step(solvers, nsteps, chunk_cycles: int = 16, use_graph: bool = True):
+BATCH_GRAPH, BATCH_FUSE = 1, 2
+
+
+def batch_step(solvers, nsteps, chunk_cycles: int = 16, use_graph: bool = True, fuse: bool = False):
     """Advance several solvers (one storage type, one stream) together with the
-    batched persistent kernels; solver k by nsteps[k] steps."""
+    batched persistent kernels; solver k by nsteps[k] steps.  fuse: the kick
+    fused with the pair of half drifts after it, where a grid allows it."""
     torch = _torch()
     lib = load()
     n = len(solvers)
@@ -318,8 +322,8 @@ def batch_step(solvers, nsteps, chunk_cycles: int = 16, use_graph: bool = True):
     scratch = torch.empty(nb, dtype=torch.uint8, device=solvers[0].device)
     ctxs = (C.c_void_p * n)(*[s._ctx for s in solvers])
     steps = (C.c_int64 * n)(*[int(k) for k in nsteps])
-    check(lib.vlasov_batch_step(ctxs, n, steps, C.c_void_p(scratch.data_ptr()), nb, int(chunk_cycles),
-                                1 if use_graph else 0))
+    flags = (BATCH_GRAPH if use_graph else 0) | (BATCH_FUSE if fuse else 0)
+    check(lib.vlasov_batch_step(ctxs, n, steps, C.c_void_p(scratch.data_ptr()), nb, int(chunk_cycles), flags))
     del scratch
 
 
@@ -327,7 +331,7 @@ class Server:
     """Continuous-batching request server over a torch-allocated device arena."""
 
     def __init__(self, arena_bytes: int, storage: int = 1, max_slots: int = 32, chunk_cycles: int = 16,
-                 use_graph: bool = True, device: int | None = None):
+                 use_graph: bool = True, device: int | None = None, fuse: bool = False):
         torch = _torch()
         lib = load()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
@@ -338,7 +342,8 @@ class Server:
         srv = C.c_void_p()
         check(lib.vlasov_server_create(C.c_void_p(self.arena.data_ptr()), int(arena_bytes),
                                        C.c_void_p(self.stream.cuda_stream), int(storage), int(max_slots),
-                                       int(chunk_cycles), 1 if use_graph else 0, C.byref(srv)))
+                                       int(chunk_cycles), (BATCH_GRAPH if use_graph else 0) | (BATCH_FUSE if fuse else 0),
+                                       C.byref(srv)))
         self._srv = srv
         self._shapes = {}
 

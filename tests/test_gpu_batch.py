@@ -76,17 +76,17 @@ def _solo(V, p, f0, n, Fext, hist=0):
 
 
 @pytest.mark.parametrize("storage", [0, 1])
-@pytest.mark.parametrize("chunk,graph", [(4, True), (16, False), (3, True)])
-def test_batch_equals_oracle_and_each_grid_alone(V, oracle, storage, chunk, graph):
+@pytest.mark.parametrize("chunk,graph,fuse", [(4, True, False), (16, False, False), (3, True, True), (5, False, True)])
+def test_batch_equals_oracle_and_each_grid_alone(V, oracle, storage, chunk, graph, fuse):
     cases = mixed_cases(storage)
-    _log(f"batch storage={storage} chunk={chunk} graph={graph}")
+    _log(f"batch storage={storage} chunk={chunk} graph={graph} fuse={fuse}")
     solvers = []
     for p, f0, n, Fext in cases:
         s = V.Solver(p, f0, hist_cap=16)
         if Fext is not None:
             s.set_external_force(Fext)
         solvers.append(s)
-    V.batch_step(solvers, [c[2] for c in cases], chunk_cycles=chunk, use_graph=graph)
+    V.batch_step(solvers, [c[2] for c in cases], chunk_cycles=chunk, use_graph=graph, fuse=fuse)
     for s, (p, f0, n, Fext) in zip(solvers, cases):
         what = (p.model, p.nx, p.np_, p.storage)
         f, h, m = s.read_f(), s.mag_history(), s.moments()
@@ -128,8 +128,8 @@ def test_batch_rejects_mixed_storage(V):
     b.close()
 
 
-def _serve(V, cases, storage, arena_bytes, max_slots=8, chunk=8):
-    srv = V.Server(arena_bytes, storage=storage, max_slots=max_slots, chunk_cycles=chunk)
+def _serve(V, cases, storage, arena_bytes, max_slots=8, chunk=8, fuse=False):
+    srv = V.Server(arena_bytes, storage=storage, max_slots=max_slots, chunk_cycles=chunk, fuse=fuse)
     tickets = []
     for p, f0, n, Fext in cases:
         tickets.append(srv.submit(p, f0, n, keep_f=True))
@@ -168,13 +168,14 @@ def test_server_results_equal_oracle_and_solo_runs(V, oracle, storage):
 
 
 @pytest.mark.parametrize("storage", [1, 0])
-def test_server_mix_of_many_requests(V, oracle, storage):
-    # 24 requests of the parameter scan (three models, uneven sides), six at a
-    # time: every result equals the oracle on the same input
-    trace = I.serving_trace(24, seed=3, sides=(64, 128, 256), steps_range=(5, 40), storage=storage)
+@pytest.mark.parametrize("fuse", [False, True])
+def test_server_mix_of_many_requests(V, oracle, storage, fuse):
+    # 24 requests of the parameter scan (three models, uneven sides up to 512),
+    # six at a time: every result equals the oracle on the same input
+    trace = I.serving_trace(24, seed=3, sides=(64, 128, 256, 512), steps_range=(5, 40), storage=storage)
     cases = [(q.params, q.initial_condition(), q.nsteps, None) for q in trace]
-    _log(f"server mix storage={storage}")
-    res = _serve(V, cases, storage, 64 << 20, max_slots=6, chunk=8)
+    _log(f"server mix storage={storage} fuse={fuse}")
+    res = _serve(V, cases, storage, 96 << 20, max_slots=6, chunk=8, fuse=fuse)
     for (r, f), (p, f0, n, _) in zip(res, cases):
         what = (p.model, p.nx, p.np_, n)
         assert r["status"] == 0 and r["steps_done"] == n
