@@ -702,14 +702,21 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
     const bool own2 = P2 && u2 < G::NRUN2 && i < nx;
     const bool own1 = pass1 && u1 < G::NRUN1;
 
+    // Interval r of block blk kicks row r of the block, runs the first half
+    // drift of row r - 1 and the second of row r - 2; rows -1 and -2 are the
+    // previous block's last two, so the pipeline runs on across the blocks of
+    // a tile and only the last block drains it (two more intervals).
+    double acc[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) acc[k] = 0.0;
+#pragma unroll
     for (int blk = 0; blk < RB; ++blk) {
         const int jb = j0 + R * blk;
         if (!FULL && R * blk >= nr) break;  // uniform
-        double acc[V];
-#pragma unroll
-        for (int k = 0; k < V; ++k) acc[k] = 0.0;
+        const bool lastb = blk + 1 == RB || (!FULL && R * (blk + 1) >= nr);  // uniform
 #pragma unroll
         for (int r = 0; r < R + 2; ++r) {
+            if (r >= R && !lastb) break;  // uniform
             if (r < R && (FULL || R * blk + r < nr)) {
                 // kick of row r into its buffer
                 settle(r + 9);
@@ -722,7 +729,7 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
                 // block's extra requests read valid rows and are unused)
                 if (r + 10 + PF < NS && (RB > 1 || r + 10 + PF < R + 10)) request(r + 10 + PF);
             }
-            if (!P2 && r >= 1 && r - 1 < R && (FULL || R * blk + r - 1 < nr) && own1) {
+            if (!P2 && (r >= 1 || blk > 0) && r - 1 < R && (FULL || R * blk + r - 1 < nr) && own1) {
                 // first half drift (table 1) of row r - 1 at the positions
                 // i0 + m2 - 4 + q, q in [0, TW + 9), that the second reads
                 const int q1 = r - 1, j = jb + q1;
@@ -745,7 +752,7 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
                 ww.y = o[1];
                 reinterpret_cast<V2 *>(mbuf + (q1 & 1) * MLD)[u1] = ww;
             }
-            if (P2 && r >= 2 && (FULL || R * blk + r - 2 < nr) && own2) {
+            if (P2 && (r >= 2 || blk > 0) && (FULL || R * blk + r - 2 < nr) && own2) {
                 // second half drift (table 2) of row r - 2: outputs i, i + 1
                 const int q2 = r - 2, j = jb + q2;
                 const double4 wd = dw2[j];
@@ -762,9 +769,20 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
 #pragma unroll
                 for (int k = 0; k < V; ++k) acc[k] = acc[k] + (double)o[k];
             }
+            if (P2 && r == 1 && blk > 0) {
+                // the previous block's sums are complete
+                if (own2) {
+                    double *prow = part + (size_t)(ty * RB + blk - 1) * nx;
+#pragma unroll
+                    for (int k = 0; k < V; ++k)
+                        if (i + k < nx) prow[i + k] = acc[k];
+                }
+#pragma unroll
+                for (int k = 0; k < V; ++k) acc[k] = 0.0;
+            }
             __syncthreads();
         }
-        if (P2 && own2) {
+        if (P2 && own2 && lastb) {
             double *prow = part + (size_t)(ty * RB + blk) * nx;
 #pragma unroll
             for (int k = 0; k < V; ++k)
