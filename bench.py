@@ -361,7 +361,8 @@ def model_leg(V, torch, workload: str, steps: int, warmup: int, shape) -> dict:
     ms = secs / steps * 1e3
     kd = us.get("kick_drift2")
     return {"workload": workload, "value": p.nx * p.np_ * steps / secs, "unit": "grid-point updates/s",
-            "ms_per_step": ms, "steps": steps, "kernels_us": us,
+            "ms_per_step": ms, "steps": steps, "launch_shape": shape_str(shape) if shape else "library default",
+            "kernels_us": us,
             "outside_fused_kernel_us_per_step": (ms * 1e3 - kd) if kd else None}
 
 
@@ -501,7 +502,7 @@ def main():
                                                 filter_strength=1.0)
     if not (args.no_extras or args.no_variants):
         # the other two models at their full sizes (per-step overhead beside the headline)
-        out["other_models"] = [model_leg(V, torch, w, max(2, args.steps // 10), 5, shape)
+        out["other_models"] = [model_leg(V, torch, w, max(2, args.steps // 10), 5, None)
                                for w in ("hmf_gaussian_2048x2048_T0.4_f64", "ring_2048x2048_f64")]
     if not args.no_copy:
         out["copy_ceiling_GBps"] = copy_ceiling(torch, V)

@@ -285,7 +285,7 @@ typedef struct {
                                   every tile differ by at most 8 columns, else the separate
                                   kernels run.  The last step of a call (kick and one half
                                   drift) always uses the separate kernels. */
-    int32_t kick_drift_blocks; /* rows of a fused tile in 16-row density blocks: 1, 2 or 4 */
+    int32_t kick_drift_blocks; /* rows of a fused tile in 16-row density blocks: 1 to 4 */
 } vlasov_tuning;
 
 /* The compiled launch shapes: writes min(cap, total) of them, *n = total. */
@@ -293,7 +293,8 @@ int vlasov_tuning_candidates(vlasov_tuning *out, int32_t cap, int32_t *n);
 
 /* Select a compiled launch shape for a context (VLASOV_E_INVAL otherwise).
  * Defaults: 128 drift threads, 16 (FP64) or 32 (FP32) kick rows, fused kick
- * and drift on tiles of 256 columns by 16 rows.  Changing kick_drift_blocks
+ * and drift on tiles of 230 columns by 32 rows where the grid gives at least
+ * 2048 such tiles, else by 16 rows.  Changing kick_drift_blocks
  * rebuilds the fused tables (synchronises the context's stream). */
 int vlasov_set_tuning(vlasov_ctx *c, const vlasov_tuning *t);
 int vlasov_get_tuning(vlasov_ctx *c, vlasov_tuning *t);
@@ -311,7 +312,10 @@ int vlasov_get_tuning(vlasov_ctx *c, vlasov_tuning *t);
  *                       after it (the single-grid fused kernel on 230-column
  *                       tiles, for members whose drift offsets allow it and
  *                       whose p axis is periodic): f is read and written once
- *                       for the three sweeps.  Off by default: on the
+ *                       for the three sweeps.  It sets each member's
+ *                       kick_drift_blocks to 1 (the batched tiles are 16
+ *                       rows tall; synchronises a member whose tuning had
+ *                       another value).  Off by default: on the
  *                       512-request serving trace it measured slower (each
  *                       fused tile is a 16-row pipeline whose latency sets the
  *                       time of every batched phase). */

@@ -43,6 +43,8 @@ int launch_kick_drift_w(vlasov_ctx *c, int ta, double h)
     switch (c->kd_rb) {
     case 4:
         return launch_kick_drift_t<T, TW, 4>(c, ta, h);
+    case 3:
+        return launch_kick_drift_t<T, TW, 3>(c, ta, h);
     case 2:
         return launch_kick_drift_t<T, TW, 2>(c, ta, h);
     default:

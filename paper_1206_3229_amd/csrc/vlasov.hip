@@ -421,7 +421,7 @@ int vlasov_init(const vlasov_params *p, const double *f0_host, void *f_dev, void
     c->tune.drift_threads = DRIFT_NT;
     c->tune.kick_rows = p->storage == VLASOV_F32 ? kick_rows<float>() : kick_rows<double>();
     c->tune.kick_drift_width = KD_TW;
-    c->tune.kick_drift_blocks = KD_RB;
+    c->tune.kick_drift_blocks = default_kd_blocks(p->nx, c->nblk);
     for (int k = 0; k < VLASOV_K_COUNT; ++k) {
         c->ms[k] = 0.0;
         c->cnt[k] = 0;
@@ -775,7 +775,9 @@ int vlasov_tuning_candidates(vlasov_tuning *out, int32_t cap, int32_t *n)
 {
     static const int nts[] = {64, 128, 256}, rs[] = {8, 16, 32};
     if (!n || cap < 0 || (cap > 0 && !out)) return fail(VLASOV_E_INVAL, "bad argument");
-    static const int kdw[] = {230, 486}, kdb[] = {1, 2, 4};
+    // the default tile first (ties in a tuner go to the earlier shape)
+    static const int kdw[] = {KD_TW, 486}, kdb[] = {KD_RB, 1, 3, 4};
+    static_assert(KD_TW == 230 && KD_RB == 2, "candidate lists hold the default once");
     int k = 0;
     for (int a : nts)
         for (int r : rs) {
@@ -799,7 +801,7 @@ int vlasov_set_tuning(vlasov_ctx *c, const vlasov_tuning *t)
     const bool nt_ok = t->drift_threads == 64 || t->drift_threads == 128 || t->drift_threads == 256;
     const bool r_ok = t->kick_rows == 8 || t->kick_rows == 16 || t->kick_rows == 32;
     const bool w_ok = t->kick_drift_width == 0 || t->kick_drift_width == 230 || t->kick_drift_width == 486;
-    const bool b_ok = t->kick_drift_blocks == 1 || t->kick_drift_blocks == 2 || t->kick_drift_blocks == 4;
+    const bool b_ok = t->kick_drift_blocks >= 1 && t->kick_drift_blocks <= 4;
     if (!nt_ok || !r_ok || !w_ok || !b_ok) return fail(VLASOV_E_INVAL, "launch shape not compiled in");
     const bool retable = t->kick_drift_blocks != c->kd_rb;
     HIP_TRY(hipStreamSynchronize(c->stream));  // the graphs of the old shape may still run

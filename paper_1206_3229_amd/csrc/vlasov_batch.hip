@@ -46,6 +46,16 @@ bool fusable(const vlasov_ctx *c)
     return c->kd_ok[0] && c->kd_rb == 1 && c->P.bc_p == VLASOV_BC_PERIODIC;
 }
 
+// The batched fused kernel runs tiles of one 16-row block: a member's fused
+// tables must be built for that height (vlasov_set_tuning rebuilds them).
+int one_block_tiles(vlasov_ctx *c)
+{
+    if (c->kd_rb == 1) return VLASOV_OK;
+    vlasov_tuning t = c->tune;
+    t.kick_drift_blocks = 1;
+    return vlasov_set_tuning(c, &t);
+}
+
 int kd_tiles(const vlasov_ctx *c) { return (int)((c->P.nx + vk::KB_KD_TW - 1) / vk::KB_KD_TW) * (int)c->nblk; }
 
 int drift_tiles(const vlasov_ctx *c)
@@ -404,7 +414,9 @@ void admit(vlasov_server *s)
         const bool gen = p.req.ic.kind != VLASOV_IC_HOST;
         int rc = vlasov_init(&p.req.p, gen ? nullptr : p.f0.data(), s->arena + off, s->arena + off + align_up(fb),
                              s->adm, &c);
-        if (rc == VLASOV_OK && gen && (rc = vlasov_generate_ic(c, &p.req.ic)) != VLASOV_OK) {
+        if (rc == VLASOV_OK && gen) rc = vlasov_generate_ic(c, &p.req.ic);
+        if (rc == VLASOV_OK && (s->flags & VLASOV_BATCH_FUSE)) rc = one_block_tiles(c);
+        if (rc != VLASOV_OK && c) {
             vlasov_destroy(c);
             c = nullptr;
         }
@@ -606,6 +618,11 @@ int vlasov_batch_step(vlasov_ctx *const *ctxs, int32_t n, const int64_t *nsteps,
         for (int b = 0; b < a; ++b)
             if (ctxs[b] == ctxs[a]) return fail(VLASOV_E_INVAL, "a context appears twice");
     }
+    if (flags & VLASOV_BATCH_FUSE)
+        for (int a = 0; a < n; ++a) {
+            const int rt = one_block_tiles(ctxs[a]);
+            if (rt != VLASOV_OK) return rt;
+        }
     Engine eng;
     int rc = eng.init((char *)scratch_dev, scratch_bytes, ctxs[0]->stream, ctxs[0]->P.storage, chunk_cycles, flags);
     if (rc != VLASOV_OK) {

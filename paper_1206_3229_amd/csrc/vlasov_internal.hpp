@@ -33,9 +33,17 @@ inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 constexpr int DRIFT_NT = 128, DRIFT_V = 2, DRIFT_PF = 4;
 // kick rows per thread (measured best on 4096^2: 16 for FP64, 32 for FP32)
 template <typename T> constexpr int kick_rows() { return sizeof(T) == 8 ? 16 : 32; }
-// fused kick and drift: default tile width and blocks; rows requested ahead
-// by the kick (FP64 within 96 VGPRs, five waves per SIMD)
-constexpr int KD_TW = 230, KD_RB = 1;
+// fused kick and drift: default tile width and blocks (FP64 needs 78 VGPRs
+// with 32-row tiles, six waves per SIMD, and 68 with 16-row ones, seven);
+// rows requested ahead by the kick
+constexpr int KD_TW = 230, KD_RB = 2;
+// 32-row tiles where the grid still gives at least this many of them, else
+// 16-row tiles (twice the workgroups, to fill the chip)
+constexpr int64_t KD_RB_MIN_TILES = 2048;
+inline int default_kd_blocks(int64_t nx, int64_t nblk)
+{
+    return ((nx + KD_TW - 1) / KD_TW) * ((nblk + KD_RB - 1) / KD_RB) >= KD_RB_MIN_TILES ? KD_RB : 1;
+}
 template <typename T> constexpr int kd_pf() { return 2; }
 // rows per thread of the filter along p
 constexpr int FILTER_R = 16;

@@ -92,10 +92,10 @@ def test_kernel_names(lib):
 def test_tuning_candidates_cover_separate_and_fused(lib):
     from paper_1206_3229_amd import vlasov as V
     cands = V.tuning_candidates()
-    assert len(cands) == len(set(cands)) == 15
+    assert len(cands) == len(set(cands)) == 17
     assert sum(1 for c in cands if c[2] == 0) == 9
     assert {c[2] for c in cands} == {0, 230, 486}
-    assert {(c[2], c[3]) for c in cands if c[2]} == {(w, b) for w in (230, 486) for b in (1, 2, 4)}
+    assert {(c[2], c[3]) for c in cands if c[2]} == {(w, b) for w in (230, 486) for b in (1, 2, 3, 4)}
 
 
 def test_workspace_holds_a_drift_table_per_substep(lib):

@@ -83,12 +83,15 @@ def test_batch_equals_oracle_and_each_grid_alone(V, oracle, storage, chunk, grap
     solvers = []
     for p, f0, n, Fext in cases:
         s = V.Solver(p, f0, hist_cap=16)
+        s.set_tuning(128, 16, 230, 2)
         if Fext is not None:
             s.set_external_force(Fext)
         solvers.append(s)
     V.batch_step(solvers, [c[2] for c in cases], chunk_cycles=chunk, use_graph=graph, fuse=fuse)
     for s, (p, f0, n, Fext) in zip(solvers, cases):
         what = (p.model, p.nx, p.np_, p.storage)
+        # the batched fused tiles are one 16-row block tall
+        assert s.get_tuning()[2:] == ((230, 1) if fuse else (230, 2)), what
         f, h, m = s.read_f(), s.mag_history(), s.moments()
         f_ref, h_ref, m_ref = _oracle(oracle, p, f0, n, Fext)
         assert np.array_equal(f, f_ref), what
@@ -208,7 +211,7 @@ def test_every_launch_shape_gives_identical_results(V, oracle):
     with pytest.raises(V.VlasovError):
         s.set_tuning(128, 16, 384)
     with pytest.raises(V.VlasovError):
-        s.set_tuning(128, 16, 230, 3)
+        s.set_tuning(128, 16, 230, 5)
     s.close()
 
 

@@ -13,7 +13,7 @@ from paper_1206_3229_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 # (kick_drift_width, kick_drift_blocks)
-SHAPES = ((0, 1), (230, 1), (230, 2), (230, 4), (486, 1), (486, 4))
+SHAPES = ((0, 1), (230, 1), (230, 2), (230, 3), (230, 4), (486, 1), (486, 4))
 
 
 @pytest.fixture(scope="module")
