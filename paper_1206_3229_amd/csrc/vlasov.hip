@@ -158,17 +158,14 @@ int density_force(vlasov_ctx *c)
     int64_t *hcount = c->at<int64_t>(c->L.hcount);
     double *mxmy = c->at<double>(c->L.mxmy);
     const double *cs = c->at<double>(c->L.cs), *sn = c->at<double>(c->L.sn);
-    const bool staged = nx <= vk::FORCE_LDS_MAX;
     switch (P.model) {
     case VLASOV_MODEL_HMF:
         launch(c, VLASOV_K_FORCE, vk::k_force_hmf, dim3(1), dim3(1024), rho, cs, sn, F, nx, c->dx, mxmy, hist, hcount,
                P.hist_cap);
         break;
     case VLASOV_MODEL_RING:
-        launch(c, VLASOV_K_FORCE, staged ? vk::k_magnetization<true> : vk::k_magnetization<false>, dim3(1),
-               dim3(1024), rho, cs, sn, nx, c->dx, mxmy, hist, hcount, P.hist_cap);
-        launch(c, VLASOV_K_FORCE, vk::k_force_ring, dim3((unsigned)((nx + 3) / 4)), dim3(256), rho,
-               c->at<double>(c->L.ringK), F, nx, c->dx);
+        launch(c, VLASOV_K_FORCE, vk::k_force_ring, dim3((unsigned)(1 + (nx + 3) / 4)), dim3(256), rho,
+               c->at<double>(c->L.ringK), F, nx, c->dx, cs, sn, mxmy, hist, hcount, P.hist_cap);
         break;
     case VLASOV_MODEL_SHEET: {
         const double K = ((2.0 * M_PI) * P.sheet_G) * c->dx;

@@ -1217,7 +1217,8 @@ static __global__ __launch_bounds__(1024) void k_force_hmf(const double *__restr
     for (int i = threadIdx.x; i < n; i += blockDim.x) F[i] = fma(my, cs[i], -(mx * sn[i]));
 }
 
-// Magnetization only (ring model).  One workgroup, wavefront 0 reduces.
+// Magnetization only (ring model, batched force phase).  One workgroup,
+// wavefront 0 reduces.
 template <bool STAGED>
 __device__ __forceinline__ void magnetization_block(const double *__restrict__ rho, const double *__restrict__ cs,
                                                     const double *__restrict__ sn, int n, double dx, double *mxmy,
@@ -1236,16 +1237,6 @@ __device__ __forceinline__ void magnetization_block(const double *__restrict__ r
         magnetization(r, c, s, n, dx, mx, my);
         if (threadIdx.x == 0) record_history(mxmy, hist, hcount, hcap, mx, my);
     }
-}
-
-template <bool STAGED>
-static __global__ __launch_bounds__(1024) void k_magnetization(const double *__restrict__ rho,
-                                                        const double *__restrict__ cs,
-                                                        const double *__restrict__ sn, int n, double dx, double *mxmy,
-                                                        double *hist, int64_t *hcount, int64_t hcap)
-{
-    __shared__ double L[STAGED ? 3 * FORCE_LDS_MAX : 1];
-    magnetization_block<STAGED>(rho, cs, sn, n, dx, mxmy, hist, hcount, hcap, L);
 }
 
 // Ring force, eq. (meanforce) with eq. (ringpot): F_i = -dx sum_k K_{(i-k)
@@ -1278,10 +1269,23 @@ __device__ __forceinline__ void force_ring_output(const double *__restrict__ rho
     if (lane == 0) F[i] = -(dx * acc);
 }
 
+// Workgroup 0 forms the magnetization (M_x, M_y) for the history instead (the
+// ring force does not use it), dispatched first so that its longer chain
+// overlaps the outputs' workgroups; launch 1 + ceil(n / 4) workgroups.
 static __global__ __launch_bounds__(256) void k_force_ring(const double *__restrict__ rho, const double *__restrict__ K,
-                                                    double *__restrict__ F, int n, double dx)
+                                                    double *__restrict__ F, int n, double dx,
+                                                    const double *__restrict__ cs, const double *__restrict__ sn,
+                                                    double *mxmy, double *hist, int64_t *hcount, int64_t hcap)
 {
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < 64) {
+            double mx, my;
+            magnetization(rho, cs, sn, n, dx, mx, my);
+            if (threadIdx.x == 0) record_history(mxmy, hist, hcount, hcap, mx, my);
+        }
+        return;
+    }
+    const int i = (blockIdx.x - 1) * 4 + (threadIdx.x >> 6);
     if (i >= n) return;
     force_ring_output(rho, K, F, n, dx, i);
 }
