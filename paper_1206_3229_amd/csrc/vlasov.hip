@@ -163,10 +163,13 @@ int density_force(vlasov_ctx *c)
         launch(c, VLASOV_K_FORCE, vk::k_force_hmf, dim3(1), dim3(1024), rho, cs, sn, F, nx, c->dx, mxmy, hist, hcount,
                P.hist_cap);
         break;
-    case VLASOV_MODEL_RING:
-        launch(c, VLASOV_K_FORCE, vk::k_force_ring, dim3((unsigned)(1 + (nx + 3) / 4)), dim3(256), rho,
-               c->at<double>(c->L.ringK), F, nx, c->dx, cs, sn, mxmy, hist, hcount, P.hist_cap);
+    case VLASOV_MODEL_RING: {
+        const int per = vk::ring_outputs_per_wg(nx);
+        launch(c, VLASOV_K_FORCE, nx <= vk::RING_LDS_MAX ? vk::k_force_ring<true> : vk::k_force_ring<false>,
+               dim3((unsigned)(1 + (nx + per - 1) / per)), dim3(256), rho, c->at<double>(c->L.ringK), F, nx, c->dx,
+               cs, sn, mxmy, hist, hcount, P.hist_cap);
         break;
+    }
     case VLASOV_MODEL_SHEET: {
         const double K = ((2.0 * M_PI) * P.sheet_G) * c->dx;
         launch(c, VLASOV_K_FORCE, nx <= vk::SHEET_LDS_MAX ? vk::k_force_sheet<true> : vk::k_force_sheet<false>,

@@ -1083,6 +1083,34 @@ static __global__ __launch_bounds__(1024) void k_density(const double *__restric
     if (lane == 0 && io < nx) rho[io] = dp * v;
 }
 
+// Stage two arrays of n doubles into LDS (whole workgroup), the sixteen loads
+// of a round per thread in flight before their LDS writes.
+__device__ __forceinline__ void stage2(double *d0, const double *__restrict__ s0, double *d1,
+                                       const double *__restrict__ s1, int n)
+{
+    const int bd = blockDim.x;
+    for (int k0 = threadIdx.x; k0 < n; k0 += 8 * bd) {
+        double v[2][8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = min(k0 + u * bd, n - 1);
+            v[0][u] = s0[k];
+            v[1][u] = s1[k];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            keep_issued(v[0][u]);
+            keep_issued(v[1][u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (k0 + u * bd < n) {
+                d0[k0 + u * bd] = v[0][u];
+                d1[k0 + u * bd] = v[1][u];
+            }
+    }
+}
+
 // Stage three arrays of n doubles into LDS (whole workgroup), the twelve
 // loads of a round per thread in flight before their LDS writes.
 __device__ __forceinline__ void stage3(double *d0, const double *__restrict__ s0, double *d1,
@@ -1270,24 +1298,53 @@ __device__ __forceinline__ void force_ring_output(const double *__restrict__ rho
 }
 
 // Workgroup 0 forms the magnetization (M_x, M_y) for the history instead (the
-// ring force does not use it), dispatched first so that its longer chain
-// overlaps the outputs' workgroups; launch 1 + ceil(n / 4) workgroups.
+// ring force does not use it), dispatched first so that its chain overlaps
+// the outputs' workgroups.  STAGED (n <= RING_LDS_MAX): every workgroup first
+// copies the arrays it reads (rho and K; rho, cos and sin for workgroup 0)
+// into LDS, whose reads in the chains are conflict-free (adjacent lanes,
+// adjacent words), and its four wavefronts then form RING_OUT_WG / 4 outputs
+// each; otherwise one output per wavefront straight from global memory.
+// Launch 1 + ceil(n / ring_outputs_per_wg(n)) workgroups of 256 threads.
+constexpr int RING_LDS_MAX = 2048;
+constexpr int RING_OUT_WG = 8;
+__host__ __device__ constexpr int ring_outputs_per_wg(int n) { return n <= RING_LDS_MAX ? RING_OUT_WG : 4; }
+
+template <bool STAGED>
 static __global__ __launch_bounds__(256) void k_force_ring(const double *__restrict__ rho, const double *__restrict__ K,
                                                     double *__restrict__ F, int n, double dx,
                                                     const double *__restrict__ cs, const double *__restrict__ sn,
                                                     double *mxmy, double *hist, int64_t *hcount, int64_t hcap)
 {
+    __shared__ double L[STAGED ? 3 * RING_LDS_MAX : 1];
     if (blockIdx.x == 0) {
+        const double *r = rho, *c = cs, *s = sn;
+        if (STAGED) {
+            stage3(L, rho, L + RING_LDS_MAX, cs, L + 2 * RING_LDS_MAX, sn, n);
+            __syncthreads();
+            r = L;
+            c = L + RING_LDS_MAX;
+            s = L + 2 * RING_LDS_MAX;
+        }
         if (threadIdx.x < 64) {
             double mx, my;
-            magnetization(rho, cs, sn, n, dx, mx, my);
+            magnetization(r, c, s, n, dx, mx, my);
             if (threadIdx.x == 0) record_history(mxmy, hist, hcount, hcap, mx, my);
         }
         return;
     }
-    const int i = (blockIdx.x - 1) * 4 + (threadIdx.x >> 6);
-    if (i >= n) return;
-    force_ring_output(rho, K, F, n, dx, i);
+    constexpr int OUT = STAGED ? RING_OUT_WG : 4;
+    const double *r = rho, *k = K;
+    if (STAGED) {
+        stage2(L, rho, L + RING_LDS_MAX, K, n);
+        __syncthreads();
+        r = L;
+        k = L + RING_LDS_MAX;
+    }
+#pragma unroll
+    for (int q = 0; q < OUT / 4; ++q) {
+        const int i = (blockIdx.x - 1) * OUT + (threadIdx.x >> 6) * (OUT / 4) + q;
+        if (i < n) force_ring_output(r, k, F, n, dx, i);
+    }
 }
 
 // Sheet force, eq. (sheetpot) with V = 2 pi G |x|: F_i = K (S - 2 P_i - rho_i),

@@ -97,9 +97,13 @@ def test_drift_matches_oracle(V, oracle, name, npass):
     assert_same(got, want, f"drift {name}")
 
 
-@pytest.mark.parametrize("name", ["hmf128", "hmf600x50_ragged", "ring", "sheet", "external", "hmf_f32"])
+# ring2048 and ring2100: the largest grid whose ring force stages its operands
+# in LDS, and one past it (straight from global memory)
+@pytest.mark.parametrize("name", ["hmf128", "hmf600x50_ragged", "ring", "ring2048", "ring2100", "sheet", "external",
+                                  "hmf_f32"])
 def test_force_and_kick_match_oracle(V, oracle, name):
     p = {"hmf128": hmf(128, 128), "hmf600x50_ragged": hmf(600, 50), "ring": ring(200, 64),
+         "ring2048": ring(2048, 16), "ring2100": ring(2100, 16),
          "sheet": sheet(300, 40, dt=0.3), "external": None, "hmf_f32": hmf(600, 50, storage=1)}[name]
     Fext = None
     if name == "external":
