@@ -61,15 +61,29 @@ __global__ void k_ic_bag_raw(double *__restrict__ raw, Grid g, Bag w)
         raw[e] = waterbag_raw(g, w, (int)(e % (size_t)g.nx), (int)(e / (size_t)g.nx));
 }
 
+// s + a[0] + a[1] + ... + a[n-1], added one by one in index order; sixteen
+// terms requested at a time.
+__device__ __forceinline__ double serial_sum(const double *__restrict__ a, int n)
+{
+    double s = 0.0;
+    int i = 0;
+    for (; i + 16 <= n; i += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = a[i + u];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s = s + v[u];
+    }
+    for (; i < n; ++i) s = s + a[i];
+    return s;
+}
+
 // Serial sum of each row (one thread per row, from i = 0).
 __global__ void k_ic_rows_raw(const double *__restrict__ raw, double *__restrict__ rows, Grid g)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= g.np) return;
-    const double *r = raw + (size_t)j * (size_t)g.nx;
-    double s = 0.0;
-    for (int i = 0; i < g.nx; ++i) s = s + r[i];
-    rows[j] = s;
+    rows[j] = serial_sum(raw + (size_t)j * (size_t)g.nx, g.nx);
 }
 
 __global__ void k_ic_rows_gauss(const double *__restrict__ e, const double *__restrict__ c,
@@ -87,8 +101,7 @@ __global__ void k_ic_rows_gauss(const double *__restrict__ e, const double *__re
 __global__ void k_ic_norm(const double *__restrict__ rows, double *__restrict__ norm, Grid g)
 {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    double s = 0.0;
-    for (int j = 0; j < g.np; ++j) s = s + rows[j];
+    const double s = serial_sum(rows, g.np);
     norm[0] = (s * g.dx) * g.dp;
 }
 
