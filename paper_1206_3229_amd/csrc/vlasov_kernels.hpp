@@ -582,6 +582,8 @@ static __global__ __launch_bounds__(256) void k_kick_filter(const T *__restrict_
 // computes 1 + 1/V stencils per output instead of 2.
 // ---------------------------------------------------------------------------
 constexpr int KD_SPR = 8;
+// rows per barrier interval of the fused kernel
+constexpr int KD_RPI = 2;
 
 // Geometry of a fused tile of TW columns: runs of two adjacent values per lane
 // in both half drifts (16-byte LDS accesses, conflict-free), W1 waves for the
@@ -607,6 +609,7 @@ struct KDGeom {
     // kicked row: column c of the range at slot c + (krel & 1), so that every
     // row's window starts at an even slot; both buffers padded for the reads
     // of the last runs (V + 10 values from slot V u)
+    static constexpr int NBUF = 2 * KD_RPI;  // rows in each LDS ring
     static constexpr int KLD = NT + 16;
     static constexpr int MLD = NRUN1 * V + 16;
     static_assert(TW % V == 0, "whole second-pass runs");
@@ -638,14 +641,12 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
     const int nr = FULL ? R * RB : min(R * RB, np - j0);  // rows of the tile
 
     // padding of the row buffers (read only by values that are never kept)
-    for (int s = G::NT + t; s < KLD; s += G::NT) {
-        kbuf[s] = T(0);
-        kbuf[KLD + s] = T(0);
-    }
-    for (int s = G::NRUN1 * V + t; s < MLD; s += G::NT) {
-        mbuf[s] = T(0);
-        mbuf[MLD + s] = T(0);
-    }
+    for (int s = G::NT + t; s < KLD; s += G::NT)
+#pragma unroll
+        for (int b = 0; b < G::NBUF; ++b) kbuf[b * KLD + s] = T(0);
+    for (int s = G::NRUN1 * V + t; s < MLD; s += G::NT)
+#pragma unroll
+        for (int b = 0; b < G::NBUF; ++b) mbuf[b * MLD + s] = T(0);
 
     // The kicked column of this lane: foot of its p shift (eq. step3), the
     // spline weights, and the element index of its first sample.
@@ -702,10 +703,14 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
     const bool own2 = P2 && u2 < G::NRUN2 && i < nx;
     const bool own1 = pass1 && u1 < G::NRUN1;
 
-    // Interval r of block blk kicks row r of the block, runs the first half
-    // drift of row r - 1 and the second of row r - 2; rows -1 and -2 are the
-    // previous block's last two, so the pipeline runs on across the blocks of
-    // a tile and only the last block drains it (two more intervals).
+    // Interval it of block blk kicks rows P it .. P it + P - 1 of the block
+    // (P = KD_RPI rows per barrier interval), runs the first half drift of the
+    // P rows before them and the second of the P rows before those; negative
+    // rows are the previous block's last ones, so the pipeline runs on across
+    // the blocks of a tile and only the last block drains it (two more
+    // intervals).  Row q's buffers are slot q mod 2P of each ring.
+    constexpr int P = KD_RPI, NI = R / P, NB = G::NBUF;
+    static_assert(R % P == 0 && (NB & (NB - 1)) == 0, "whole intervals per block, ring of 2^k rows");
     double acc[V];
 #pragma unroll
     for (int k = 0; k < V; ++k) acc[k] = 0.0;
@@ -715,61 +720,73 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
         if (!FULL && R * blk >= nr) break;  // uniform
         const bool lastb = blk + 1 == RB || (!FULL && R * (blk + 1) >= nr);  // uniform
 #pragma unroll
-        for (int r = 0; r < R + 2; ++r) {
-            if (r >= R && !lastb) break;  // uniform
-            if (r < R && (FULL || R * blk + r < nr)) {
-                // kick of row r into its buffer
-                settle(r + 9);
-                const T Dk1 = second_diff(w + r + 5);
-                T y = spline(ka, kb, kg, kd, w[r + 4], w[r + 5], Dk, Dk1);
-                Dk = Dk1;
-                if (!kick_in) y = colin ? y : T(0);
-                kbuf[(r & 1) * KLD + (krel[jb + r] & 1) + t] = y;
-                // samples of the next block are requested too (the last
-                // block's extra requests read valid rows and are unused)
-                if (r + 10 + PF < NS && (RB > 1 || r + 10 + PF < R + 10)) request(r + 10 + PF);
-            }
-            if (!P2 && (r >= 1 || blk > 0) && r - 1 < R && (FULL || R * blk + r - 1 < nr) && own1) {
-                // first half drift (table 1) of row r - 1 at the positions
-                // i0 + m2 - 4 + q, q in [0, TW + 9), that the second reads
-                const int q1 = r - 1, j = jb + q1;
-                const int rel = krel[j];
-                const T *src = kbuf + (q1 & 1) * KLD + rel + (rel & 1);
-                const double4 w1 = dw1[j];
-                T o[V];
-                spline_run<T, V>(src, u1, (T)w1.x, (T)w1.y, (T)w1.z, (T)w1.w, o);
-                if (BCX == BC_ZERO) {
-                    const int lo = i0 + dm2[j] - 4;  // position of first-pass value 0
-                    if (!(lo >= 0 && lo + G::MIDN <= nx)) {
-                        const int q = lo + V * u1;
+        for (int it = 0; it < NI + 2; ++it) {
+            if (it >= NI && !lastb) break;  // uniform
 #pragma unroll
-                        for (int k = 0; k < V; ++k)
-                            if (q + k < 0 || q + k >= nx) o[k] = T(0);
-                    }
+            for (int s = 0; s < P; ++s) {
+                const int r = P * it + s;
+                if (it < NI && (FULL || R * blk + r < nr)) {
+                    // kick of row r into its buffer
+                    settle(r + 9);
+                    const T Dk1 = second_diff(w + r + 5);
+                    T y = spline(ka, kb, kg, kd, w[r + 4], w[r + 5], Dk, Dk1);
+                    Dk = Dk1;
+                    if (!kick_in) y = colin ? y : T(0);
+                    kbuf[(r & (NB - 1)) * KLD + (krel[jb + r] & 1) + t] = y;
+                    // samples of the next block are requested too (the last
+                    // block's extra requests read valid rows and are unused)
+                    if (r + 10 + PF < NS && (RB > 1 || r + 10 + PF < R + 10)) request(r + 10 + PF);
                 }
-                V2 ww;
-                ww.x = o[0];
-                ww.y = o[1];
-                reinterpret_cast<V2 *>(mbuf + (q1 & 1) * MLD)[u1] = ww;
             }
-            if (P2 && (r >= 2 || blk > 0) && (FULL || R * blk + r - 2 < nr) && own2) {
-                // second half drift (table 2) of row r - 2: outputs i, i + 1
-                const int q2 = r - 2, j = jb + q2;
-                const double4 wd = dw2[j];
-                T o[V];
-                spline_run<T, V>(mbuf + (q2 & 1) * MLD, u2, (T)wd.x, (T)wd.y, (T)wd.z, (T)wd.w, o);
-                if (FULL) {
+#pragma unroll
+            for (int s = 0; s < P; ++s) {
+                const int q1 = P * (it - 1) + s;
+                if (!P2 && (it >= 1 || blk > 0) && it - 1 < NI && (FULL || R * blk + q1 < nr) && own1) {
+                    // first half drift (table 1) of row q1 at the positions
+                    // i0 + m2 - 4 + q, q in [0, TW + 9), that the second reads
+                    const int j = jb + q1;
+                    const int rel = krel[j];
+                    const T *src = kbuf + (q1 & (NB - 1)) * KLD + rel + (rel & 1);
+                    const double4 w1 = dw1[j];
+                    T o[V];
+                    spline_run<T, V>(src, u1, (T)w1.x, (T)w1.y, (T)w1.z, (T)w1.w, o);
+                    if (BCX == BC_ZERO) {
+                        const int lo = i0 + dm2[j] - 4;  // position of first-pass value 0
+                        if (!(lo >= 0 && lo + G::MIDN <= nx)) {
+                            const int q = lo + V * u1;
+#pragma unroll
+                            for (int k = 0; k < V; ++k)
+                                if (q + k < 0 || q + k >= nx) o[k] = T(0);
+                        }
+                    }
                     V2 ww;
                     ww.x = o[0];
                     ww.y = o[1];
-                    *reinterpret_cast<V2 *>(fout + (size_t)j * nx + i) = ww;
-                } else {
-                    store_run<T, V>(fout + (size_t)j * nx, i, nx, o);
+                    reinterpret_cast<V2 *>(mbuf + (q1 & (NB - 1)) * MLD)[u1] = ww;
                 }
-#pragma unroll
-                for (int k = 0; k < V; ++k) acc[k] = acc[k] + (double)o[k];
             }
-            if (P2 && r == 1 && blk > 0) {
+#pragma unroll
+            for (int s = 0; s < P; ++s) {
+                const int q2 = P * (it - 2) + s;
+                if (P2 && (it >= 2 || blk > 0) && (FULL || R * blk + q2 < nr) && own2) {
+                    // second half drift (table 2) of row q2: outputs i, i + 1
+                    const int j = jb + q2;
+                    const double4 wd = dw2[j];
+                    T o[V];
+                    spline_run<T, V>(mbuf + (q2 & (NB - 1)) * MLD, u2, (T)wd.x, (T)wd.y, (T)wd.z, (T)wd.w, o);
+                    if (FULL) {
+                        V2 ww;
+                        ww.x = o[0];
+                        ww.y = o[1];
+                        *reinterpret_cast<V2 *>(fout + (size_t)j * nx + i) = ww;
+                    } else {
+                        store_run<T, V>(fout + (size_t)j * nx, i, nx, o);
+                    }
+#pragma unroll
+                    for (int k = 0; k < V; ++k) acc[k] = acc[k] + (double)o[k];
+                }
+            }
+            if (P2 && it == 1 && blk > 0) {
                 // the previous block's sums are complete
                 if (own2) {
                     double *prow = part + (size_t)(ty * RB + blk - 1) * nx;
@@ -806,8 +823,8 @@ static __global__ __launch_bounds__(KDGeom<TW>::NT) void k_kick_drift(
     int ntx, int nty)
 {
     using G = KDGeom<TW>;
-    __shared__ __attribute__((aligned(16))) T kbuf[2 * G::KLD];  // two kicked rows
-    __shared__ __attribute__((aligned(16))) T mbuf[2 * G::MLD];  // two first-pass rows
+    __shared__ __attribute__((aligned(16))) T kbuf[G::NBUF * G::KLD];  // ring of kicked rows
+    __shared__ __attribute__((aligned(16))) T mbuf[G::NBUF * G::MLD];  // ring of first-pass rows
     int tx, ty;
     if (!xcd_tile(ntx, nty, tx, ty)) return;
     // every row of the tile in the grid, and rows of an even length (aligned
@@ -1767,8 +1784,8 @@ static __global__ __launch_bounds__(KDGeom<KB_KD_TW>::NT) void kb_kick_drift(con
                                                                              const Cycle *__restrict__ cy)
 {
     using G = KDGeom<KB_KD_TW>;
-    __shared__ __attribute__((aligned(16))) T kbuf[2 * G::KLD];
-    __shared__ __attribute__((aligned(16))) T mbuf[2 * G::MLD];
+    __shared__ __attribute__((aligned(16))) T kbuf[G::NBUF * G::KLD];
+    __shared__ __attribute__((aligned(16))) T mbuf[G::NBUF * G::MLD];
     const int n = cy->n;
     const int total = cy->off_kd[n];
     for (int e = blockIdx.x; e < total; e += gridDim.x) {
