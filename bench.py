@@ -485,11 +485,24 @@ def main():
         if alt:
             shape32, _ = pick_shape(alt)
             p32, secs32, prof32, _, _ = run_gpu(alt, args.steps, args.warmup, torch, V, shape32)
+            kd32 = prof32.get("kick_drift2", (0.0, 0))
+            roof32 = None
+            if kd32[1]:
+                # the fused kernel of the FP32 leg against the same peak: 4-byte f
+                avg32 = kd32[0] / kd32[1] * 1e-3
+                bpp32 = algorithmic_bytes_per_point("kick_drift2", 4)
+                ach32 = bpp32 * p32.nx * p32.np_ / avg32 / 1e9
+                tr32 = traced_launch_us(alt, "kick_drift2", shape32)
+                roof32 = {"bound": "hbm", "kernel": "kick_drift2", "achieved": ach32, "peak": HBM_PEAK_GBPS,
+                          "unit": "GB/s", "frac": ach32 / HBM_PEAK_GBPS,
+                          "traffic": measured_traffic(alt, "kick_drift2", shape32) if shape32 else None,
+                          "bytes_per_point": bpp32, "avg_launch_us": avg32 * 1e6, "trace_avg_launch_us": tr32}
             out["fp32_storage"] = {"workload": alt, "value": p32.nx * p32.np_ * args.steps / secs32,
                                    "launch_shape": shape32,
                                    "ms_per_step": secs32 / args.steps * 1e3,
                                    "kernels_us": {k: (v[0] / v[1] * 1e3 if v[1] else None)
                                                   for k, v in prof32.items()},
+                                   "roofline": roof32,
                                    "error_vs_fp64": fp32_error_vs_fp64(torch, V, args.workload, alt, shape,
                                                                        shape32)}
     if not (args.no_extras or args.no_variants):
