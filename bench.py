@@ -251,9 +251,9 @@ def run_sequential_fp64(V, torch, trace, ics, keep):
     return out
 
 
-def run_server(V, trace, ics, arrivals, keep, arena_bytes, max_slots, chunk):
+def run_server(V, trace, ics, arrivals, keep, arena_bytes, max_slots, chunk, fuse=True):
     import threading
-    srv = V.Server(arena_bytes, storage=I.STORAGE_F32, max_slots=max_slots, chunk_cycles=chunk)
+    srv = V.Server(arena_bytes, storage=I.STORAGE_F32, max_slots=max_slots, chunk_cycles=chunk, fuse=fuse)
     tickets = [None] * len(trace)
     start = time.perf_counter()
 
@@ -340,6 +340,7 @@ def serving(V, torch, nreq, seed=0, arena_bytes=2 << 30, max_slots=48, chunk=64)
     return {
         "requests": nreq, "total_updates": total, "storage": "f32 f, f64 density/force/diagnostics",
         "arena_bytes": arena_bytes, "max_slots": max_slots, "chunk_cycles": chunk,
+        "fused_kick_drift": True,
         "burst": {"makespan_s": span, "updates_per_s": total / span,
                   "p50_s": _pct([r[0]["t_done"] - r[0]["t_submit"] for r in burst], 50),
                   "p99_s": _pct([r[0]["t_done"] - r[0]["t_submit"] for r in burst], 99)},

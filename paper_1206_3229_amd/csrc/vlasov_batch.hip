@@ -9,6 +9,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -24,7 +25,6 @@ using namespace vlasov_detail;
 namespace {
 
 // Persistent launch widths (workgroups) of the four batched phases.
-constexpr int KB_DRIFT_WG = 2048, KB_DENS_WG = 1024, KB_FORCE_WG = 256, KB_KICK_WG = 2048, KB_KD_WG = 1024;
 constexpr int KB_FORCE_NT = 1024;
 
 size_t set_bytes(int K) { return align_up(sizeof(vk::GridDesc) * vk::BATCH_MAX + sizeof(vk::Cycle) * (size_t)K); }
@@ -131,6 +131,15 @@ class Engine {
         storage_ = storage;
         K_ = K;
         graph_ = graph;
+        // each persistent launch has as many workgroups as the chip holds at once
+        int dev_id = 0, ncu = 0;
+        HIP_TRY(hipGetDevice(&dev_id));
+        HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id));
+        if (storage == VLASOV_F32) {
+            HIP_TRY(size_grids<float>(ncu));
+        } else {
+            HIP_TRY(size_grids<double>(ncu));
+        }
         for (int s = 0; s < 2; ++s) {
             HIP_TRY(hipHostMalloc((void **)&host_[s], set_bytes(K), hipHostMallocDefault));
             HIP_TRY(hipEventCreateWithFlags(&ev_[s], hipEventDisableTiming));
@@ -245,17 +254,39 @@ class Engine {
     }
 
   private:
+    // Resident workgroups of each persistent kernel (occupancy times CUs).
+    template <typename K>
+    static hipError_t resident(K kernel, int threads, int ncu, int &out)
+    {
+        int nb = 0;
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0);
+        out = std::max(1, nb) * ncu;
+        return e;
+    }
+
+    template <typename T>
+    hipError_t size_grids(int ncu)
+    {
+        hipError_t e = resident(vk::kb_drift<T, DRIFT_NT, DRIFT_V, DRIFT_PF>, DRIFT_NT, ncu, wg_drift_);
+        if (e == hipSuccess) e = resident(vk::kb_density, 256, ncu, wg_dens_);
+        if (e == hipSuccess) e = resident(vk::kb_force, KB_FORCE_NT, ncu, wg_force_);
+        if (e == hipSuccess) e = resident(vk::kb_kick<T, kick_rows<T>()>, 256, ncu, wg_kick_);
+        if (e == hipSuccess)
+            e = resident(vk::kb_kick_drift<T, kd_pf<T>()>, vk::KDGeom<vk::KB_KD_TW>::NT, ncu, wg_kd_);
+        return e;
+    }
+
     template <typename T>
     void launch_cycles_t(char *dset, hipStream_t st)
     {
         const vk::GridDesc *gd = reinterpret_cast<const vk::GridDesc *>(dset);
         const vk::Cycle *cy = reinterpret_cast<const vk::Cycle *>(dset + sizeof(vk::GridDesc) * vk::BATCH_MAX);
         for (int k = 0; k < K_; ++k) {
-            vk::kb_drift<T, DRIFT_NT, DRIFT_V, DRIFT_PF><<<KB_DRIFT_WG, DRIFT_NT, 0, st>>>(gd, cy + k);
-            vk::kb_density<<<KB_DENS_WG, 256, 0, st>>>(gd, cy + k);
-            vk::kb_force<<<KB_FORCE_WG, KB_FORCE_NT, 0, st>>>(gd, cy + k);
-            vk::kb_kick<T, kick_rows<T>()><<<KB_KICK_WG, 256, 0, st>>>(gd, cy + k);
-            if (fuse_) vk::kb_kick_drift<T, kd_pf<T>()><<<KB_KD_WG, vk::KDGeom<vk::KB_KD_TW>::NT, 0, st>>>(gd, cy + k);
+            vk::kb_drift<T, DRIFT_NT, DRIFT_V, DRIFT_PF><<<wg_drift_, DRIFT_NT, 0, st>>>(gd, cy + k);
+            vk::kb_density<<<wg_dens_, 256, 0, st>>>(gd, cy + k);
+            vk::kb_force<<<wg_force_, KB_FORCE_NT, 0, st>>>(gd, cy + k);
+            vk::kb_kick<T, kick_rows<T>()><<<wg_kick_, 256, 0, st>>>(gd, cy + k);
+            if (fuse_) vk::kb_kick_drift<T, kd_pf<T>()><<<wg_kd_, vk::KDGeom<vk::KB_KD_TW>::NT, 0, st>>>(gd, cy + k);
         }
     }
 
@@ -280,6 +311,7 @@ class Engine {
     hipStream_t cap_ = nullptr;
     int set_ = 0;
     bool fuse_ = false;  // the fused kick and drift pair for the members that allow it
+    int wg_drift_ = 1, wg_dens_ = 1, wg_force_ = 1, wg_kick_ = 1, wg_kd_ = 1;  // persistent grid sizes
 
   public:
     // failure handling tests: the chunk with this index (from 0) fails after
