@@ -281,7 +281,7 @@ def run_server(V, trace, ics, arrivals, keep, arena_bytes, max_slots, chunk, fus
     return results
 
 
-def serving(V, torch, nreq, seed=0, arena_bytes=2 << 30, max_slots=128, chunk=64):
+def serving(V, torch, nreq, seed=0, arena_bytes=2 << 30, max_slots=256, chunk=64):
     trace = I.serving_trace(nreq, rate=math.inf, seed=seed, storage=I.STORAGE_F32)
     # each request carries its initial-condition spec (U, M0, noise, seed); the
     # server, and the sequential baseline, build f0 on the device inside the

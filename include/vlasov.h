@@ -303,7 +303,7 @@ int vlasov_get_tuning(vlasov_ctx *c, vlasov_tuning *t);
  * Batches: many contexts stepped together (one persistent launch per phase).
  * ------------------------------------------------------------------------- */
 
-#define VLASOV_BATCH_MAX 128
+#define VLASOV_BATCH_MAX 256
 
 /* Flags of batched stepping and of the server (the `flags` arguments):
  *   VLASOV_BATCH_GRAPH  capture the chunk's launches into a HIP graph once and

@@ -638,7 +638,7 @@ size_t vlasov_batch_scratch_bytes(int32_t chunk_cycles)
 int vlasov_batch_step(vlasov_ctx *const *ctxs, int32_t n, const int64_t *nsteps, void *scratch_dev,
                       size_t scratch_bytes, int32_t chunk_cycles, int32_t flags)
 {
-    if (!ctxs || !nsteps || n < 1 || n > vk::BATCH_MAX) return fail(VLASOV_E_INVAL, "need 1..VLASOV_BATCH_MAX (128) contexts");
+    if (!ctxs || !nsteps || n < 1 || n > vk::BATCH_MAX) return fail(VLASOV_E_INVAL, "need 1..VLASOV_BATCH_MAX (256) contexts");
     for (int a = 0; a < n; ++a) {
         if (!ctxs[a]) return fail(VLASOV_E_INVAL, "NULL context");
         if (nsteps[a] < 0) return fail(VLASOV_E_INVAL, "nsteps must be >= 0");
@@ -693,7 +693,7 @@ int vlasov_server_create(void *arena_dev, size_t arena_bytes, void *hip_stream, 
 {
     if (!arena_dev || !out || ((uintptr_t)arena_dev % ALIGN)) return fail(VLASOV_E_INVAL, "bad arena or output");
     if (storage != VLASOV_F64 && storage != VLASOV_F32) return fail(VLASOV_E_INVAL, "unknown storage");
-    if (max_slots < 1 || max_slots > vk::BATCH_MAX) return fail(VLASOV_E_INVAL, "max_slots must be in [1, VLASOV_BATCH_MAX = 128]");
+    if (max_slots < 1 || max_slots > vk::BATCH_MAX) return fail(VLASOV_E_INVAL, "max_slots must be in [1, VLASOV_BATCH_MAX = 256]");
     const size_t tb = vlasov_server_table_bytes(chunk_cycles);
     if (!tb) return fail(VLASOV_E_INVAL, "chunk_cycles must be in [1, 4096]");
     if (arena_bytes <= tb) return fail(VLASOV_E_INVAL, "arena smaller than the server tables");

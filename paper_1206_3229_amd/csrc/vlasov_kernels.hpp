@@ -1613,7 +1613,7 @@ static __global__ __launch_bounds__(64) void k_mom_final(const double *__restric
 // over the work items of all members; per-grid arithmetic is exactly that of
 // the single-grid kernels, whatever workgroup processes a tile.
 // ---------------------------------------------------------------------------
-constexpr int BATCH_MAX = 128;
+constexpr int BATCH_MAX = 256;
 
 enum { DRIFT_NONE = 0, DRIFT_FIRST = 1, DRIFT_PAIR = 2, DRIFT_LAST = 3 };
 

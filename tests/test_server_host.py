@@ -65,7 +65,7 @@ def test_create_arguments(V):
     tb = lib.vlasov_server_table_bytes(16)
     assert lib.vlasov_server_create(C.c_void_p(1 << 20), tb, None, 1, 8, 16, 1, C.byref(srv)) == V.E_INVAL
     assert lib.vlasov_server_create(C.c_void_p((1 << 20) + 8), 1 << 30, None, 1, 8, 16, 1, C.byref(srv)) == V.E_INVAL
-    assert lib.vlasov_server_create(C.c_void_p(1 << 20), 1 << 30, None, 1, 129, 16, 1, C.byref(srv)) == V.E_INVAL
+    assert lib.vlasov_server_create(C.c_void_p(1 << 20), 1 << 30, None, 1, 257, 16, 1, C.byref(srv)) == V.E_INVAL
     assert lib.vlasov_server_create(C.c_void_p(1 << 20), 1 << 30, None, 2, 8, 16, 1, C.byref(srv)) == V.E_INVAL
     assert lib.vlasov_server_create(C.c_void_p(1 << 20), 1 << 30, None, 1, 8, 0, 1, C.byref(srv)) == V.E_INVAL
 
