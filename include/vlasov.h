@@ -310,8 +310,10 @@ int vlasov_get_tuning(vlasov_ctx *c, vlasov_tuning *t);
  *                       replay it;
  *   VLASOV_BATCH_FUSE   run each member's kick fused with the pair of half drifts
  *                       after it (the single-grid fused kernel on 230-column
- *                       tiles, for members whose drift offsets allow it and
- *                       whose p axis is periodic): f is read and written once
+ *                       tiles, or on 182-column tiles with 56 columns of
+ *                       slack for members whose drift offsets spread by 9 to
+ *                       56 columns inside a 16-row tile; members with a
+ *                       periodic p axis): f is read and written once
  *                       for the three sweeps.  It sets each member's
  *                       kick_drift_blocks to 1 (the batched tiles are 16
  *                       rows tall; synchronises a member whose tuning had

@@ -239,7 +239,9 @@ int kick_then_drift(vlasov_ctx *c, int k, int tb, double h, bool filt)
 // per pair (k, k + 1 mod nsub) of drift tables: row j's two half drifts move
 // its window by o_j = m_k,j + m_k+1,j columns; per tile the start of its
 // kicked column range relative to the tile, per row the offset of its window
-// in that range.  Sets kd_ok[k].
+// in that range.  Sets kd_ok[k] (the single-grid kernels' slack) and
+// kd_spread[k]; the tables are filled for spreads up to the batched kernel's
+// wider slack.
 void build_kd_tables(vlasov_ctx *c, int rb)
 {
     const vlasov_params &P = c->P;
@@ -260,7 +262,7 @@ void build_kd_tables(vlasov_ctx *c, int rb)
                 hi = std::max(hi, ma[j] + mb[j]);
             }
             spread = std::max(spread, hi - lo);
-            if (hi - lo > vk::KD_SPR) continue;  // not fusable; the tables are unused
+            if (hi - lo > vk::KD_SPR_WIDE) continue;  // not fusable; the tables are unused
             for (int64_t j = j0; j < j1; ++j) rel[j] = (int32_t)(ma[j] + mb[j] - lo);
             int64_t s0 = lo - 8;
             if (P.bc_x == VLASOV_BC_PERIODIC) {
@@ -270,6 +272,7 @@ void build_kd_tables(vlasov_ctx *c, int rb)
             base[b] = (int32_t)s0;
         }
         c->kd_ok[k] = spread <= vk::KD_SPR;
+        c->kd_spread[k] = spread;
     }
     c->kd_rb = rb;
 }

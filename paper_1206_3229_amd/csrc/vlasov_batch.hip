@@ -40,11 +40,14 @@ struct Member {
 
 // The fused kick and drift pair runs on a member whose drift offsets vary
 // little enough inside its 16-row tiles (tables built for one block per
-// tile) and whose p axis is periodic.
+// tile) and whose p axis is periodic: spreads up to 8 columns on tiles of 230
+// columns, up to 56 on tiles of 182.
 bool fusable(const vlasov_ctx *c)
 {
-    return c->kd_ok[0] && c->kd_rb == 1 && c->P.bc_p == VLASOV_BC_PERIODIC;
+    return c->kd_spread[0] <= vk::KD_SPR_WIDE && c->kd_rb == 1 && c->P.bc_p == VLASOV_BC_PERIODIC;
 }
+
+bool kd_wide(const vlasov_ctx *c) { return c->kd_spread[0] > vk::KD_SPR; }
 
 // The batched fused kernel runs tiles of one 16-row block: a member's fused
 // tables must be built for that height (vlasov_set_tuning rebuilds them).
@@ -56,7 +59,11 @@ int one_block_tiles(vlasov_ctx *c)
     return vlasov_set_tuning(c, &t);
 }
 
-int kd_tiles(const vlasov_ctx *c) { return (int)((c->P.nx + vk::KB_KD_TW - 1) / vk::KB_KD_TW) * (int)c->nblk; }
+int kd_tiles(const vlasov_ctx *c)
+{
+    const int tw = kd_wide(c) ? vk::KB_KD_TW_WIDE : vk::KB_KD_TW;
+    return (int)((c->P.nx + tw - 1) / tw) * (int)c->nblk;
+}
 
 int drift_tiles(const vlasov_ctx *c)
 {
@@ -113,6 +120,7 @@ vk::GridDesc describe(const vlasov_ctx *c)
     g.sheetK = ((2.0 * M_PI) * c->P.sheet_G) * c->dx;
     g.kbase = c->at<int32_t>(c->L.kd_base);
     g.krel = c->at<int32_t>(c->L.kd_rel);
+    g.kd_wide = kd_wide(c) ? 1 : 0;
     return g;
 }
 

@@ -109,6 +109,9 @@ struct vlasov_ctx {
     // fused on tiles of kd_rb blocks (drift shifts of every tile within the
     // kicked halo)
     bool kd_ok[vlasov_detail::MAX_SUB];
+    // largest spread of the drift offsets o_j inside one such tile (the
+    // batched fused kernel has a wider-slack tile for spreads up to 56)
+    int64_t kd_spread[vlasov_detail::MAX_SUB];
     int kd_rb;
     // profiling
     bool prof;

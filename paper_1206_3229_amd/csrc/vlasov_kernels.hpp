@@ -585,20 +585,22 @@ constexpr int KD_SPR = 8;
 // rows per barrier interval of the fused kernel
 constexpr int KD_RPI = 2;
 
-// Geometry of a fused tile of TW columns: runs of two adjacent values per lane
-// in both half drifts (16-byte LDS accesses, conflict-free), W1 waves for the
-// first half drift (TW + 9 values per row) and W2 for the second (TW outputs),
-// one kicked column per lane over the KW = TW + 18 + SPR columns the windows
-// need.  Every wave kicks; TW = 230 (four waves) and 486 (eight) make the
-// kicked columns and both half drifts fill their waves.
-template <int TW>
+// Geometry of a fused tile of TW columns whose rows' windows lie within SPR
+// columns of slack: runs of two adjacent values per lane in both half drifts
+// (16-byte LDS accesses, conflict-free), W1 waves for the first half drift
+// (TW + 9 values per row) and W2 for the second (TW outputs), one kicked
+// column per lane over the KW = TW + 18 + SPR columns the windows need.  Every
+// wave kicks; TW = 230 (four waves) and 486 (eight) with 8 columns of slack,
+// and TW = 182 with 56, make the kicked columns and both half drifts fill
+// their waves.
+template <int TW, int SPR = KD_SPR>
 struct KDGeom {
     static constexpr int V = 2;                          // outputs per lane in the half drifts
     static constexpr int MIDN = TW + 9;                  // first-pass values per row
     static constexpr int NRUN1 = (MIDN + V - 1) / V;     // first-pass lanes
     static constexpr int NRUN2 = TW / V;                 // second-pass lanes
     static constexpr int W1 = (NRUN1 + 63) / 64, W2 = (NRUN2 + 63) / 64;
-    static constexpr int KW = TW + 18 + KD_SPR;          // kicked columns per row
+    static constexpr int KW = TW + 18 + SPR;             // kicked columns per row
     static constexpr int NWK = (KW + 63) / 64;
     static constexpr int NW = NWK > W1 + W2 ? NWK : W1 + W2;  // waves
     static constexpr int NT = 64 * NW;
@@ -613,7 +615,7 @@ struct KDGeom {
     static constexpr int KLD = NT + 16;
     static constexpr int MLD = NRUN1 * V + 16;
     static_assert(TW % V == 0, "whole second-pass runs");
-    static_assert(KD_SPR + 1 + V * (NRUN1 - 1) + V + 10 <= KLD, "first-pass reads stay in the kicked row");
+    static_assert(SPR + 1 + V * (NRUN1 - 1) + V + 10 <= KLD, "first-pass reads stay in the kicked row");
     static_assert(V * (NRUN2 - 1) + V + 10 <= MLD, "second-pass reads stay in the first-pass row");
 };
 
@@ -621,7 +623,7 @@ struct KDGeom {
 // waves run the first half drift (or only kick).  The two roles are separate
 // code, so that the wait of each for its requested kick samples counts only
 // its own memory operations.
-template <typename T, int BCX, int BCP, int TW, int PF, int RB, bool FULL, bool P2>
+template <typename T, int BCX, int BCP, int TW, int PF, int RB, bool FULL, bool P2, int SPR = KD_SPR>
 __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__restrict__ fout,
                                                 const double *__restrict__ F, double dt, double dp,
                                                 const int32_t *__restrict__ dm2, const double4 *__restrict__ dw1,
@@ -629,7 +631,7 @@ __device__ __forceinline__ void kick_drift_tile(const T *__restrict__ fin, T *__
                                                 const int32_t *__restrict__ krel, double *__restrict__ part, int nx,
                                                 int np, int tx, int ty, int rw, T *kbuf, T *mbuf)
 {
-    using G = KDGeom<TW>;
+    using G = KDGeom<TW, SPR>;
     using V2 = typename Vec2<T>::type;
     constexpr int V = G::V, R = ROWS_PER_BLOCK, KLD = G::KLD, MLD = G::MLD;
     constexpr int NS = R + 10 + PF;  // window slots: samples of a block plus those requested ahead
@@ -1628,8 +1630,9 @@ struct GridDesc {
     int64_t *hcount;
     int64_t hcap;
     int32_t nx, np, nblk, model, bc_x, bc_p;
+    int32_t kd_wide;  // fused kick and drift on the wide-slack tiles
     double dx, dp, dt, sheetK;
-    const int32_t *kbase, *krel;  // fused kick and drift: tables of 256-column, 16-row tiles
+    const int32_t *kbase, *krel;  // fused kick and drift: tables of the member's 16-row tiles
 };
 
 struct Cycle {
@@ -1777,22 +1780,33 @@ static __global__ __launch_bounds__(256) void kb_kick(const GridDesc *__restrict
 
 // The kick fused with the two half drifts after it (the second of one step,
 // the first of the next) for the members whose tables allow it: tiles of 230
-// columns by 16 rows, as the single-grid kernel.  Periodic p only.
+// columns by 16 rows with 8 columns of slack, as the single-grid kernel, or,
+// for a member whose drift offsets spread more inside a tile (coarse p, fine
+// x, long steps), tiles of 182 columns with 56 of slack (the same 256 kicked
+// columns and four waves, more kicked columns per output).  Periodic p only.
 constexpr int KB_KD_TW = 230;
+constexpr int KB_KD_TW_WIDE = 182, KD_SPR_WIDE = 56;
+// (five waves per SIMD: the FP64 form fits them without spilling)
 template <typename T, int PF>
-static __global__ __launch_bounds__(KDGeom<KB_KD_TW>::NT) void kb_kick_drift(const GridDesc *__restrict__ gd,
-                                                                             const Cycle *__restrict__ cy)
+static __global__ __launch_bounds__(KDGeom<KB_KD_TW>::NT) __attribute__((amdgpu_waves_per_eu(5)))
+void kb_kick_drift(const GridDesc *__restrict__ gd, const Cycle *__restrict__ cy)
 {
     using G = KDGeom<KB_KD_TW>;
+    using GW = KDGeom<KB_KD_TW_WIDE, KD_SPR_WIDE>;
+    static_assert(G::NT == GW::NT && G::NW == GW::NW && G::W1 == GW::W1 && G::W2 == GW::W2 && G::KLD == GW::KLD &&
+                      G::NBUF == GW::NBUF,
+                  "one workgroup shape and wave roles for both tile widths");
+    constexpr int MLD = G::MLD > GW::MLD ? G::MLD : GW::MLD;
     __shared__ __attribute__((aligned(16))) T kbuf[G::NBUF * G::KLD];
-    __shared__ __attribute__((aligned(16))) T mbuf[G::NBUF * G::MLD];
+    __shared__ __attribute__((aligned(16))) T mbuf[G::NBUF * MLD];
     const int n = cy->n;
     const int total = cy->off_kd[n];
     for (int e = blockIdx.x; e < total; e += gridDim.x) {
         const int a = find_member(cy->off_kd, n, e);
         const GridDesc &g = gd[cy->slot[a]];
         const int li = e - cy->off_kd[a];
-        const int ntx = (g.nx + KB_KD_TW - 1) / KB_KD_TW;
+        const int tw = g.kd_wide ? KB_KD_TW_WIDE : KB_KD_TW;
+        const int ntx = (g.nx + tw - 1) / tw;
         const int tx = li % ntx, ty = li / ntx;
         const int kin = cy->kin[a];
         const T *fin = (const T *)g.f[kin];
@@ -1801,27 +1815,35 @@ static __global__ __launch_bounds__(KDGeom<KB_KD_TW>::NT) void kb_kick_drift(con
         const int rw = G::role(threadIdx.x >> 6, e % G::NW);
         const bool p2 = rw >= G::W1 && rw < G::W1 + G::W2;
         __syncthreads();  // the previous item's LDS rows are consumed
-#define KDB(BX, FL, P)                                                                                               \
-    kick_drift_tile<T, BX, BC_PERIODIC, KB_KD_TW, PF, 1, FL, P>(fin, fout, g.Fkick, g.dt, g.dp, g.dm, g.dw, g.dw,         \
-                                                                g.kbase, g.krel, g.part, g.nx, g.np, tx, ty, rw, kbuf, mbuf)
-#define KDB2(BX, FL)     \
-    if (p2)              \
-        KDB(BX, FL, true); \
-    else                 \
-        KDB(BX, FL, false)
-        if (g.bc_x == BC_PERIODIC) {
-            if (full) {
-                KDB2(BC_PERIODIC, true);
-            } else {
-                KDB2(BC_PERIODIC, false);
-            }
+#define KDB(TW, SPR, BX, FL, P)                                                                                     \
+    kick_drift_tile<T, BX, BC_PERIODIC, TW, PF, 1, FL, P, SPR>(fin, fout, g.Fkick, g.dt, g.dp, g.dm, g.dw, g.dw,   \
+                                                               g.kbase, g.krel, g.part, g.nx, g.np, tx, ty, rw, kbuf, \
+                                                               mbuf)
+#define KDB2(TW, SPR, BX, FL)     \
+    if (p2)                       \
+        KDB(TW, SPR, BX, FL, true); \
+    else                          \
+        KDB(TW, SPR, BX, FL, false)
+#define KDB4(TW, SPR)                              \
+    if (g.bc_x == BC_PERIODIC) {                   \
+        if (full) {                                \
+            KDB2(TW, SPR, BC_PERIODIC, true);      \
+        } else {                                   \
+            KDB2(TW, SPR, BC_PERIODIC, false);     \
+        }                                          \
+    } else {                                       \
+        if (full) {                                \
+            KDB2(TW, SPR, BC_ZERO, true);          \
+        } else {                                   \
+            KDB2(TW, SPR, BC_ZERO, false);         \
+        }                                          \
+    }
+        if (g.kd_wide) {
+            KDB4(KB_KD_TW_WIDE, KD_SPR_WIDE)
         } else {
-            if (full) {
-                KDB2(BC_ZERO, true);
-            } else {
-                KDB2(BC_ZERO, false);
-            }
+            KDB4(KB_KD_TW, KD_SPR)
         }
+#undef KDB4
 #undef KDB2
 #undef KDB
     }

@@ -48,6 +48,14 @@ def mixed_cases(storage):
     p = I.Params(I.MODEL_SHEET, 500, 37, -10.0, 10.0, -4.0, 4.0, 0.02, bc_x=I.BC_ZERO, bc_p=I.BC_ZERO,
                  storage=storage)
     out.append((p, I.waterbag(p, 1.0, 0.5, 1e-4, 7), 6, None))
+    # coarse p, fine x, long steps: drift offsets spreading by 20 columns
+    # inside a 16-row tile (the batched fused kernel's wide-slack tiles; the
+    # EXTERNAL grid above spreads by 20 too, on a periodic x axis)
+    p = I.Params(I.MODEL_SHEET, 700, 40, -10.0, 10.0, -4.0, 4.0, 0.2, bc_x=I.BC_ZERO, storage=storage)
+    out.append((p, I.waterbag(p, 1.0, 0.5, 1e-4, 8), 7, None))
+    # a spread beyond the wide tiles' slack (about 110 columns): never fused
+    p = I.Params(I.MODEL_HMF, 1000, 32, -math.pi, math.pi, -2.5, 2.5, 0.3, storage=storage)
+    out.append((p, I.waterbag(p, th0, p0, 1e-4, 9), 3, None))
     return out
 
 
@@ -150,14 +158,14 @@ def _serve(V, cases, storage, arena_bytes, max_slots=8, chunk=8, fuse=False):
     return [results[t] for t in tickets]
 
 
-@pytest.mark.parametrize("storage", [1, 0])
-def test_server_results_equal_oracle_and_solo_runs(V, oracle, storage):
+@pytest.mark.parametrize("storage,fuse", [(1, False), (0, False), (1, True)])
+def test_server_results_equal_oracle_and_solo_runs(V, oracle, storage, fuse):
     cases = [c for c in mixed_cases(storage) if c[3] is None]
     # arena for roughly two requests at a time: admission must queue
     need = max(V.request_footprint(c[0]) for c in cases)
     tables = V.load().vlasov_server_table_bytes(8)
-    _log(f"server storage={storage}, arena {tables + 2 * need} bytes")
-    res = _serve(V, cases, storage, tables + 2 * need + 4096)
+    _log(f"server storage={storage} fuse={fuse}, arena {tables + 2 * need} bytes")
+    res = _serve(V, cases, storage, tables + 2 * need + 4096, fuse=fuse)
     for (r, f), (p, f0, n, _) in zip(res, cases):
         what = (p.model, p.nx, p.np_, p.storage)
         assert r["status"] == 0 and r["steps_done"] == n
