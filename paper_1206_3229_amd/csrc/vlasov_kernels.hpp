@@ -1212,8 +1212,8 @@ __device__ inline void record_history(double *mxmy, double *hist, int64_t *hcoun
 constexpr int FORCE_LDS_MAX = 4096;  // nx up to which rho, cos, sin are staged in LDS
 
 // HMF force, eq. (hmfmeanforce): F_i = -sin(x_i) M_x + cos(x_i) M_y.  One
-// workgroup; wavefront 0 forms (M_x, M_y).  L: 3 FORCE_LDS_MAX doubles (STAGED).
-template <bool STAGED>
+// workgroup; wavefront 0 forms (M_x, M_y).  L: 3 SMAX doubles (STAGED, n <= SMAX).
+template <bool STAGED, int SMAX = FORCE_LDS_MAX>
 __device__ __forceinline__ void force_hmf_block(const double *__restrict__ rho, const double *__restrict__ cs,
                                                 const double *__restrict__ sn, double *__restrict__ F, int n,
                                                 double dx, double *mxmy, double *hist, int64_t *hcount, int64_t hcap,
@@ -1221,11 +1221,11 @@ __device__ __forceinline__ void force_hmf_block(const double *__restrict__ rho, 
 {
     const double *r = rho, *c = cs, *s = sn;
     if (STAGED) {
-        stage3(L, rho, L + FORCE_LDS_MAX, cs, L + 2 * FORCE_LDS_MAX, sn, n);
+        stage3(L, rho, L + SMAX, cs, L + 2 * SMAX, sn, n);
         __syncthreads();
         r = L;
-        c = L + FORCE_LDS_MAX;
-        s = L + 2 * FORCE_LDS_MAX;
+        c = L + SMAX;
+        s = L + 2 * SMAX;
     }
     if (threadIdx.x < 64) {
         double mx, my;
@@ -1265,19 +1265,19 @@ static __global__ __launch_bounds__(1024) void k_force_hmf(const double *__restr
 }
 
 // Magnetization only (ring model, batched force phase).  One workgroup,
-// wavefront 0 reduces.
-template <bool STAGED>
+// wavefront 0 reduces.  L: 3 SMAX doubles (STAGED, n <= SMAX).
+template <bool STAGED, int SMAX = FORCE_LDS_MAX>
 __device__ __forceinline__ void magnetization_block(const double *__restrict__ rho, const double *__restrict__ cs,
                                                     const double *__restrict__ sn, int n, double dx, double *mxmy,
                                                     double *hist, int64_t *hcount, int64_t hcap, double *L)
 {
     const double *r = rho, *c = cs, *s = sn;
     if (STAGED) {
-        stage3(L, rho, L + FORCE_LDS_MAX, cs, L + 2 * FORCE_LDS_MAX, sn, n);
+        stage3(L, rho, L + SMAX, cs, L + 2 * SMAX, sn, n);
         __syncthreads();
         r = L;
-        c = L + FORCE_LDS_MAX;
-        s = L + 2 * FORCE_LDS_MAX;
+        c = L + SMAX;
+        s = L + 2 * SMAX;
     }
     if (threadIdx.x < 64) {
         double mx, my;
@@ -1720,9 +1720,15 @@ static __global__ __launch_bounds__(256) void kb_density(const GridDesc *__restr
 
 // Work items per member: HMF and sheet one workgroup; ring ceil(nx/16)
 // workgroups of 16 outputs plus one for the magnetization; EXTERNAL none.
-constexpr int BATCH_FORCE_LDS = SHEET_LDS_WORDS > 3 * FORCE_LDS_MAX ? SHEET_LDS_WORDS : 3 * FORCE_LDS_MAX;
+// Arrays are staged in LDS for grids up to BATCH_FORCE_STAGE columns (48 KB,
+// and at most 64 VGPRs: two workgroups per compute unit, so that the many
+// ring items of a cycle run two at a time on each unit).
+constexpr int BATCH_FORCE_STAGE = 2048;
+constexpr int BATCH_SHEET_WORDS = ((BATCH_FORCE_STAGE + 63) / 64) * 65;
+constexpr int BATCH_FORCE_LDS = BATCH_SHEET_WORDS > 3 * BATCH_FORCE_STAGE ? BATCH_SHEET_WORDS : 3 * BATCH_FORCE_STAGE;
 
-static __global__ __launch_bounds__(1024) void kb_force(const GridDesc *__restrict__ gd, const Cycle *__restrict__ cy)
+static __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+void kb_force(const GridDesc *__restrict__ gd, const Cycle *__restrict__ cy)
 {
     __shared__ double L[BATCH_FORCE_LDS];
     __shared__ double M[2];
@@ -1734,12 +1740,13 @@ static __global__ __launch_bounds__(1024) void kb_force(const GridDesc *__restri
         const int li = e - cy->off_force[a];
         __syncthreads();
         if (g.model == 0) {
-            if (g.nx <= FORCE_LDS_MAX)
-                force_hmf_block<true>(g.rho, g.cs, g.sn, g.F, g.nx, g.dx, g.mxmy, g.hist, g.hcount, g.hcap, L, M);
+            if (g.nx <= BATCH_FORCE_STAGE)
+                force_hmf_block<true, BATCH_FORCE_STAGE>(g.rho, g.cs, g.sn, g.F, g.nx, g.dx, g.mxmy, g.hist,
+                                                         g.hcount, g.hcap, L, M);
             else
                 force_hmf_block<false>(g.rho, g.cs, g.sn, g.F, g.nx, g.dx, g.mxmy, g.hist, g.hcount, g.hcap, L, M);
         } else if (g.model == 2) {
-            if (g.nx <= SHEET_LDS_MAX)
+            if (g.nx <= BATCH_FORCE_STAGE)
                 force_sheet_block<true>(g.rho, g.F, g.nx, g.sheetK, L);
             else
                 force_sheet_block<false>(g.rho, g.F, g.nx, g.sheetK, L);
@@ -1748,8 +1755,9 @@ static __global__ __launch_bounds__(1024) void kb_force(const GridDesc *__restri
             if (li < nb) {
                 const int i = li * 16 + (threadIdx.x >> 6);
                 if (i < g.nx) force_ring_output(g.rho, g.K, g.F, g.nx, g.dx, i);
-            } else if (g.nx <= FORCE_LDS_MAX) {
-                magnetization_block<true>(g.rho, g.cs, g.sn, g.nx, g.dx, g.mxmy, g.hist, g.hcount, g.hcap, L);
+            } else if (g.nx <= BATCH_FORCE_STAGE) {
+                magnetization_block<true, BATCH_FORCE_STAGE>(g.rho, g.cs, g.sn, g.nx, g.dx, g.mxmy, g.hist, g.hcount,
+                                                             g.hcap, L);
             } else {
                 magnetization_block<false>(g.rho, g.cs, g.sn, g.nx, g.dx, g.mxmy, g.hist, g.hcount, g.hcap, L);
             }
