@@ -318,8 +318,8 @@ int vlasov_get_tuning(vlasov_ctx *c, vlasov_tuning *t);
  *                       kick_drift_blocks to 1 (the batched tiles are 16
  *                       rows tall; synchronises a member whose tuning had
  *                       another value).  Requested by the caller (the
- *                       benchmark's server uses it: 1.40 against 1.31-1.36
- *                       e11 updates/s on the 512-request burst). */
+ *                       benchmark's server uses it: faster than the separate
+ *                       phases on its 512-request burst). */
 enum { VLASOV_BATCH_GRAPH = 1, VLASOV_BATCH_FUSE = 2 };
 
 /* Bytes of device scratch for batched stepping in chunks of chunk_cycles
