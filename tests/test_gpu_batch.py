@@ -113,6 +113,47 @@ def test_batch_equals_oracle_and_each_grid_alone(V, oracle, storage, chunk, grap
         s.close()
 
 
+def _drift_spread(p):
+    """Largest spread of the summed drift offsets o_j = 2 m_j over the rows of
+    a 16-row tile (plain splitting: both half drifts share one table), m_j the
+    foot cell of the half drift of row j with the tie rule of the oracle."""
+    dx = (p.xmax - p.xmin) / p.nx
+    dp = (p.pmax - p.pmin) / p.np_
+    pj = p.pmin + np.arange(p.np_) * dp
+    xi = -(pj * (p.dt / 2)) / dx
+    m = np.floor(xi)
+    m = np.where(xi - m >= 1, m + 1, m)
+    o = 2 * m
+    return int(max(o[j:j + 16].max() - o[j:j + 16].min() for j in range(0, p.np_, 16)))
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_fused_batch_at_the_wide_tiles_slack(V, oracle, storage):
+    # offsets spreading by exactly the wide tiles' 56 columns of slack (the
+    # last kicked column of a tile is read) and by 58 (never fused), beside a
+    # member on the narrow tiles, in one fused batch
+    th0, p0 = I.waterbag_halfwidths(0.5, 0.69)
+    cases = []
+    for k, (nx, dt, want) in enumerate(((1000, 0.225, 56), (1000, 0.23, 58), (128, 0.1, 4))):
+        p = I.Params(I.MODEL_HMF, nx, 48, -math.pi, math.pi, -2.5, 2.5, dt, storage=storage)
+        assert _drift_spread(p) == want
+        cases.append((p, I.waterbag(p, th0, p0, 1e-4, 20 + k), 3 + k, None))
+    _log(f"fused batch at the wide slack, storage={storage}")
+    solvers = [V.Solver(p, f0, hist_cap=8) for p, f0, _, _ in cases]
+    V.batch_step(solvers, [c[2] for c in cases], chunk_cycles=2, use_graph=True, fuse=True)
+    for s, (p, f0, n, Fext) in zip(solvers, cases):
+        what = (p.nx, p.dt, p.storage)
+        f, h, m = s.read_f(), s.mag_history(), s.moments()
+        f_ref, h_ref, m_ref = _oracle(oracle, p, f0, n, Fext)
+        assert np.array_equal(f, f_ref), what
+        assert np.array_equal(h, h_ref), what
+        assert_moments(m, m_ref, what)
+        f_solo, m_solo, _ = _solo(V, p, f0, n, Fext)
+        assert np.array_equal(f, f_solo), what
+        assert m == m_solo
+        s.close()
+
+
 def test_batch_then_single_steps_continue(V):
     # a context stepped in a batch can go on with vlasov_step
     p, f0, _ = I.hmf_waterbag_small()
